@@ -1,0 +1,315 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names the paper passage or the mathematical fact it relies on.  Expected values
+are computed here from closed forms, by brute-force exact path lengths (tests/refs.py), by
+analytic ellipsoid chords, or from invariants; none is produced by the GPU path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2503_16741_amd import synth
+import refs
+
+PAR_SAD, PAR_SDD = 1.0e7, 2.0e7      # parallel-beam limit (Section 2.2: large SAD and SDD)
+
+
+def fan(n=1, nu=4, du=1.0, theta=0.0, sad=500.0, sdd=1000.0, dx=1.0, **kw):
+    return synth.Geometry(kind="fan2d", det="flat", nx=n, ny=n, nz=1, dx=dx, dy=dx, dz=dx,
+                          nu=nu, nv=1, du=du, dv=1.0,
+                          n_views=np.size(theta), theta=theta, sad=sad, sdd=sdd, **kw)
+
+
+def cone(n=4, nz=None, nu=8, nv=8, du=1.0, dv=1.0, theta=0.0, sad=500.0, sdd=1000.0,
+         kind="cone", det="flat", dx=1.0, **kw):
+    return synth.Geometry(kind=kind, det=det, nx=n, ny=n, nz=n if nz is None else nz,
+                          dx=dx, dy=dx, dz=dx, nu=nu, nv=nv, du=du, dv=dv,
+                          n_views=np.size(theta), theta=theta, sad=sad, sdd=sdd, **kw)
+
+
+def trapezoid_cell_integrals(t, edges):
+    """Cell averages of the unit trapezoid with corners t (sorted) by adaptive Gauss-Kronrod
+    quadrature split at the corners -- a quadrature, not the antiderivative the oracle uses."""
+    from scipy.integrate import quad
+
+    def f(s):
+        return min(max(min((s - t[0]) / (t[1] - t[0]), (t[3] - s) / (t[3] - t[2])), 0.0), 1.0)
+
+    out = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        pts = [p for p in t if lo < p < hi]
+        val, _ = quad(f, lo, hi, points=pts or None, epsabs=1e-15, epsrel=1e-13, limit=200)
+        out.append(val / (hi - lo))
+    return np.array(out)
+
+
+# ---- P1: a single voxel at the isocentre, closed form --------------------------------
+
+def test_p1_single_voxel_closed_form(orc):
+    """dx = dy = 1 mm at the isocentre, theta = 0, SAD 500, SDD 1000, flat, du = 1 with cell
+    edges on the integers.  At theta = 0, u = SDD x / (SAD - y), so the corners project to
+    +-SDD*0.5/(SAD -+ 0.5); the amplitude is dy = 1 (ray along -y).  Cell values are the
+    trapezoid's cell integrals; their sum is the trapezoid's area."""
+    g = fan(n=1, nu=4)
+    y = orc.forward(g, np.ones((1, 1)))[0]
+    a, b = 1000 * 0.5 / 499.5, 1000 * 0.5 / 500.5
+    t = np.array([-a, -b, b, a])
+    want = trapezoid_cell_integrals(t, np.arange(-2.0, 2.5, 1.0))
+    np.testing.assert_allclose(y, want, rtol=0, atol=1e-13)
+    assert y.sum() == pytest.approx((a + b), rel=1e-13)      # trapezoid area (t3+t2-t1-t0)/2
+    assert y[1] == pytest.approx(0.9997504995, abs=1e-9)
+
+
+def test_p1_direction_conventions(orc):
+    """Readings of Table 1: theta turns the gantry counter-clockwise and e_u = +x at theta=0.
+    At theta = 90 deg the source is at (-SAD, 0) and e_u = +y, so a small voxel at (0, +10)
+    projects to u = SDD*10/SAD; at theta = 0 a voxel at (+10, 0) projects to u = +SDD*10/SAD."""
+    n, dx = 41, 0.5
+    for theta, (ix, iy) in ((0.0, (20 + 20, 20)), (math.pi / 2, (20, 20 + 20))):
+        g = fan(n=n, dx=dx, nu=200, du=0.5, theta=theta)
+        img = np.zeros((n, n))
+        img[iy, ix] = 1.0
+        y = orc.forward(g, img)[0]
+        centre = np.sum(y * ((np.arange(200) - 99.5) * 0.5)) / y.sum()
+        assert centre == pytest.approx(1000 * 10 / 500, abs=0.01)
+
+
+# ---- P2: parallel-beam exactness against exact path lengths --------------------------
+
+@pytest.mark.parametrize("theta_deg", [0.0, 30.0, 45.0, 90.0, 137.0, 251.0])
+def test_p2_parallel_2d_sf_exact(orc, theta_deg):
+    """In the parallel limit the SF trapezoid times l_phi0 is exactly the chord profile of a
+    rectangle, so SF equals the cell-averaged exact integral (brute force)."""
+    rng = np.random.default_rng(1)
+    g = fan(n=5, nu=24, du=0.5, theta=math.radians(theta_deg), sad=PAR_SAD, sdd=PAR_SDD,
+            dx=0.7)
+    img = rng.random((5, 5))
+    y = orc.forward(g, img)[0]
+    ref = refs.piecewise_exact(orc, g, img, 0)
+    assert np.max(np.abs(y - ref)) <= 1e-6 * np.max(ref)
+
+
+@pytest.mark.parametrize("theta_deg", [0.0, 90.0, 180.0])
+def test_p2_parallel_2d_dd_exact_on_axes(orc, theta_deg):
+    """DD is exact in the parallel limit when rays run along a grid axis."""
+    rng = np.random.default_rng(2)
+    g = fan(n=5, nu=24, du=0.5, theta=math.radians(theta_deg), sad=PAR_SAD, sdd=PAR_SDD,
+            dx=0.7)
+    img = rng.random((5, 5))
+    y = orc.forward(g, img, method="dd")[0]
+    ref = refs.piecewise_exact(orc, g, img, 0)
+    assert np.max(np.abs(y - ref)) <= 1e-6 * np.max(ref)
+    assert np.max(np.abs(y - orc.forward(g, img, method="sf")[0])) <= 1e-6 * np.max(ref)
+
+
+@pytest.mark.parametrize("theta_deg", [0.0, 33.0, 90.0, 200.0])
+def test_p2_parallel_3d_sf_exact(orc, theta_deg):
+    """3D circular cone beam in the parallel limit (no cone angle): the axial trapezoid
+    becomes the slab's rectangle and the polar amplitude is 1, so SF-TT is exact."""
+    rng = np.random.default_rng(3)
+    g = cone(n=4, nu=20, nv=14, du=0.6, dv=0.7, theta=math.radians(theta_deg),
+             sad=PAR_SAD, sdd=PAR_SDD, dx=0.6)
+    vol = rng.random((4, 4, 4))
+    y = orc.forward(g, vol)[0]
+    ref = refs.piecewise_exact(orc, g, vol, 0)
+    assert np.max(np.abs(y - ref)) <= 1e-6 * np.max(ref)
+
+
+@pytest.mark.parametrize("phi_deg", [-20.0, 12.0])
+def test_p2_parallel_tilted_sf_exact(orc, phi_deg):
+    """Non-circular pose with theta = 0 and an off-plane tilt phi, parallel limit: rays are
+    tilted in the y-z plane only, the footprint is rect(u) x trapezoid(v) with plateau
+    dy / cos(elevation) (tilt below 45 deg, dy = dz), which is exactly SF-TT with the per-cell
+    polar amplitude.  This pins the axial corners, the polar amplitude and phi's sense."""
+    rng = np.random.default_rng(4)
+    g = cone(n=4, nu=16, nv=20, du=0.6, dv=0.5, theta=0.0, sad=PAR_SAD, sdd=PAR_SDD,
+             kind="cone_noncirc", phi=math.radians(phi_deg), dx=0.6)
+    vol = rng.random((4, 4, 4))
+    y = orc.forward(g, vol)[0]
+    ref = refs.piecewise_exact(orc, g, vol, 0)
+    assert np.max(np.abs(y - ref)) <= 1e-6 * np.max(ref)
+
+
+# ---- P3: mass conservation ----------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["sf", "dd"])
+@pytest.mark.parametrize("theta_deg", [0.0, 27.0, 45.0, 118.0])
+def test_p3_mass_conservation(orc, method, theta_deg):
+    """Parallel limit, detector covering the object: sum_i y_i du = M sum_n x_n dx dy (2D),
+    sum_ij y_ij du dv = M^2 sum_n x_n dx dy dz (3D), M = SDD/SAD."""
+    rng = np.random.default_rng(5)
+    g2 = fan(n=6, nu=40, du=0.5, theta=math.radians(theta_deg), sad=PAR_SAD, sdd=PAR_SDD)
+    img = rng.random((6, 6))
+    y = orc.forward(g2, img, method=method)
+    assert y.sum() * g2.du == pytest.approx(2.0 * img.sum() * 1.0, rel=1e-6)
+    g3 = cone(n=4, nu=24, nv=16, du=0.6, dv=0.6, theta=math.radians(theta_deg),
+              sad=PAR_SAD, sdd=PAR_SDD)
+    vol = rng.random((4, 4, 4))
+    y3 = orc.forward(g3, vol, method=method)
+    assert y3.sum() * 0.36 == pytest.approx(4.0 * vol.sum(), rel=1e-6)
+
+
+# ---- P4: adjoint identity (Eq. 2, matched pair) --------------------------------------
+
+ADJ_CASES = [
+    ("sf", dict(kind="fan2d")), ("dd", dict(kind="fan2d")),
+    ("sf", dict(kind="fan2d", det="curved")), ("dd", dict(kind="fan2d", det="curved")),
+    ("sf", dict(kind="cone")), ("dd", dict(kind="cone")),
+    ("sf", dict(kind="cone", det="curved")), ("dd", dict(kind="cone", det="curved")),
+    ("sf", dict(kind="cone_noncirc")),
+]
+
+
+@pytest.mark.parametrize("method,kw", ADJ_CASES)
+def test_p4_adjoint_identity(orc, method, kw):
+    """<A x, y> = <x, A^T y> (the backprojector is the exact transpose, Eq. 2)."""
+    rng = np.random.default_rng(6)
+    nv = 1 if kw["kind"] == "fan2d" else 9
+    nviews = 7
+    extra = {}
+    if kw["kind"] == "cone_noncirc":
+        extra = dict(phi=rng.uniform(-0.05, 0.05, nviews), psi=rng.uniform(-0.05, 0.05, nviews),
+                     x_src=rng.uniform(-3, 3, nviews), z_src=rng.uniform(-3, 3, nviews))
+    g = synth.Geometry(kind=kw["kind"], det=kw.get("det", "flat"), nx=7, ny=6, nz=5,
+                       dx=0.9, dy=1.1, dz=1.0, nu=23, nv=nv, du=1.3, dv=1.2, n_views=nviews,
+                       theta=rng.uniform(0, 2 * math.pi, nviews), sad=60.0, sdd=110.0,
+                       x_ofst=0.7, y_ofst=-0.4, z_ofst=0.3, u_ofst=0.45, v_ofst=-0.3, **extra)
+    x = rng.random(g.vol_shape)
+    y = rng.random(g.sino_shape)
+    lhs = np.sum(orc.forward(g, x, method=method) * y)
+    rhs = np.sum(x * orc.adjoint(g, y, method=method))
+    assert lhs > 0
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ---- P5: symmetries ------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["sf", "dd"])
+def test_p5_rotation_by_90(orc, method):
+    """Rotating the object by +90 deg (counter-clockwise) and the gantry by +90 deg leaves
+    the projection unchanged (square grid, circular scan)."""
+    rng = np.random.default_rng(7)
+    th = np.array([0.2, 1.1, 2.9])
+    g0 = cone(n=6, nz=3, nu=21, nv=7, du=0.9, dv=0.9, theta=th, sad=40.0, sdd=80.0)
+    g1 = cone(n=6, nz=3, nu=21, nv=7, du=0.9, dv=0.9, theta=th + math.pi / 2, sad=40.0,
+              sdd=80.0)
+    vol = rng.random((3, 6, 6))
+    # new(ix, iy) = old(R^-1 (x, y)): x' = -y, y' = x  ->  new[iy', ix'] = old[iy, ix] with
+    # ix' = n-1-iy, iy' = ix
+    rot = np.empty_like(vol)
+    for iy in range(6):
+        for ix in range(6):
+            rot[:, ix, 5 - iy] = vol[:, iy, ix]
+    y0 = orc.forward(g0, vol, method=method)
+    y1 = orc.forward(g1, rot, method=method)
+    assert np.max(np.abs(y0 - y1)) <= 1e-11 * np.max(y0)
+
+
+@pytest.mark.parametrize("method", ["sf", "dd"])
+def test_p5_mirror(orc, method):
+    """Mirroring the object in x at theta = 0 mirrors the projection in u."""
+    rng = np.random.default_rng(8)
+    g = cone(n=6, nz=3, nu=21, nv=7, du=0.9, dv=0.9, theta=0.0, sad=40.0, sdd=80.0)
+    vol = rng.random((3, 6, 6))
+    y0 = orc.forward(g, vol, method=method)
+    y1 = orc.forward(g, vol[:, :, ::-1], method=method)
+    assert np.max(np.abs(y0 - y1[:, :, ::-1])) <= 1e-12 * np.max(y0)
+
+
+# ---- P6: reductions -------------------------------------------------------------------
+
+def test_p6_noncircular_reduces_to_circular(orc):
+    """Non-circular with phi = psi = 0 is the circular geometry (Section 2.2), bitwise."""
+    rng = np.random.default_rng(9)
+    th = rng.uniform(0, 6.3, 5)
+    a = cone(n=5, nu=17, nv=11, theta=th, sad=50.0, sdd=90.0, x_src=0.4, z_src=-0.8)
+    b = cone(n=5, nu=17, nv=11, theta=th, sad=50.0, sdd=90.0, x_src=0.4, z_src=-0.8,
+             kind="cone_noncirc", phi=0.0, psi=0.0)
+    vol = rng.random((5, 5, 5))
+    assert np.array_equal(orc.forward(a, vol), orc.forward(b, vol))
+    y = rng.random(a.sino_shape)
+    assert np.array_equal(orc.adjoint(a, y), orc.adjoint(b, y))
+
+
+def test_p6_scalar_vs_vector_and_batch(orc):
+    """A scalar parameter equals the same value repeated per view (Section 2.2); batch items
+    are independent."""
+    rng = np.random.default_rng(10)
+    th = rng.uniform(0, 6.3, 4)
+    a = cone(n=5, nu=17, nv=11, theta=th, sad=50.0, sdd=90.0, u_ofst=0.3)
+    b = cone(n=5, nu=17, nv=11, theta=th, sad=np.full(4, 50.0), sdd=np.full(4, 90.0),
+             u_ofst=np.full(4, 0.3))
+    vol = rng.random((2, 5, 5, 5))
+    ya, yb = orc.forward(a, vol), orc.forward(b, vol)
+    assert np.array_equal(ya, yb)
+    assert np.array_equal(ya[1], orc.forward(a, vol[1]))
+
+
+def test_p6_single_slice_3d_reduces_to_2d(orc):
+    """3D with a single slice and a single detector row whose height is the slice's
+    magnified thickness equals 2D (parallel limit: the axial trapezoid is then that row)."""
+    rng = np.random.default_rng(11)
+    th = np.array([0.0, 0.4, 2.2])
+    g2 = fan(n=6, nu=30, du=0.5, theta=th, sad=PAR_SAD, sdd=PAR_SDD)
+    g3 = cone(n=6, nz=1, nu=30, nv=1, du=0.5, dv=2.0, theta=th, sad=PAR_SAD, sdd=PAR_SDD)
+    img = rng.random((6, 6))
+    for m in ("sf", "dd"):
+        y2 = orc.forward(g2, img, method=m)
+        y3 = orc.forward(g3, img[None], method=m)[:, 0, :]
+        assert np.max(np.abs(y2 - y3)) <= 1e-6 * np.max(y2)      # fan residual at SAD 1e7
+
+
+# ---- P7: brute force on tiny grids (approximation bound) ----------------------------
+
+@pytest.mark.parametrize("det", ["flat", "curved"])
+def test_p7_brute_force_cone(orc, det):
+    """Cone beam with config-like magnification: SF and DD approximate the cell-averaged
+    exact line integral; the SF error is bounded and shrinks towards the parallel limit."""
+    rng = np.random.default_rng(12)
+    vol = rng.random((6, 6, 6))
+    errs = {}
+    for sad in (60.0, 600.0, 6000.0):
+        g = cone(n=6, nu=20, nv=16, du=0.8,
+                 dv=0.8, theta=np.array([0.35, 1.2]), sad=sad, sdd=1.5 * sad, det=det,
+                 dx=0.5)
+        ref = refs.brute_force(orc, g, vol, [0, 1], sub_u=32, sub_v=32)
+        for m in ("sf", "dd"):
+            y = orc.forward(g, vol, method=m)
+            errs[(m, sad)] = np.max(np.abs(y - ref)) / np.max(ref)
+    assert errs[("sf", 60.0)] < 0.03
+    assert errs[("dd", 60.0)] < 0.08
+    assert errs[("sf", 6000.0)] < errs[("sf", 60.0)]
+    assert errs[("sf", 6000.0)] < 0.02
+
+
+# ---- P8: analytic ellipsoids ----------------------------------------------------------
+
+def test_p8_analytic_ellipsoids(orc):
+    """SF of a partial-volume voxelised ellipsoid phantom approaches the analytic
+    cell-averaged line integrals, and the error falls when the grid is refined."""
+    ells = synth.random_ellipsoids(3, 3, r_max=7.0, z_max=5.0, axis_range=(1.5, 4.0))
+    errs = []
+    for n, dx in ((32, 0.5), (64, 0.25)):
+        g = synth.Geometry(kind="cone", det="flat", nx=n, ny=n, nz=n, dx=dx, dy=dx, dz=dx,
+                           nu=40, nv=24, du=0.8, dv=0.8, n_views=2,
+                           theta=np.array([0.3, 1.9]), sad=100.0, sdd=160.0)
+        vol = synth.voxelize_ellipsoids(ells, n, n, n, dx, dx, dx, sub=4)
+        y = orc.forward(g, vol)
+        ref = refs.ellipsoid_cell_average(g, ells, [0, 1], sub_u=6, sub_v=6)
+        errs.append(np.sqrt(np.mean((y - ref) ** 2)) / np.max(ref))
+    assert errs[0] < 0.01
+    assert errs[1] < 0.5 * errs[0]
+
+
+# ---- P9: empty and outside the field of view ----------------------------------------
+
+def test_p9_empty_and_outside(orc):
+    g = cone(n=8, nu=6, nv=4, du=0.5, dv=0.5, theta=np.array([0.0, 0.5]), sad=50.0,
+             sdd=100.0)
+    assert not np.any(orc.forward(g, np.zeros(g.vol_shape)))
+    y = np.ones(g.sino_shape)
+    x = orc.adjoint(g, y)
+    # corner voxels at |x| = 3.5 mm project beyond the 3 mm-wide detector at both views
+    assert x[4, 0, 0] == 0.0 and x[4, 7, 7] == 0.0
+    assert x[4, 3, 3] > 0.0
