@@ -1,0 +1,144 @@
+/*
+ * ctproj.h -- C ABI of the MI355X (gfx950) separable-footprint / distance-driven CT projector.
+ *
+ * The library computes the forward projection y = A x (paper, Section 2.3, Eq. 1) and the
+ * matched back projection x = A^T y (Eq. 2) of a voxel volume for 2D fan-beam, 3D circular
+ * cone-beam and 3D non-circular cone-beam scans (Section 2.2, Table 1), with flat or curved
+ * (cylindrical, centred on the source) detectors.  Two projector models are provided
+ * (Section 2.3): the separable footprint (SF; trapezoid x trapezoid, "SF-TT", in 3D) and
+ * distance driven (DD).  The system matrix is never stored; every call recomputes it.
+ *
+ * Data layout (dense, caller-owned device memory, FP32):
+ *   volume    [batch][nz][ny][nx]       x fastest   (2D: [batch][ny][nx])
+ *   sinogram  [batch][n_views][nv][nu]  u fastest   (2D: [batch][n_views][nu])
+ * Voxel (ix, iy, iz) is centred at (x_ofst + (ix-(nx-1)/2) dx, y_ofst + (iy-(ny-1)/2) dy,
+ * z_ofst + (iz-(nz-1)/2) dz); detector column i at u = (i-(nu-1)/2) du - u_ofst and row j at
+ * v = (j-(nv-1)/2) dv - v_ofst (Table 1).  At theta = 0 the source is at (x_src, SAD, z_src),
+ * the detector centre at (0, SAD-SDD, 0), e_u = +x, e_v = +z; the gantry pose is
+ * R = Rz(theta) Rx(phi) Ry(psi) (Section 2.2: rotation order y -> x -> z), all counter-
+ * clockwise.  A curved detector is an arc of radius SDD about the source; u is arc length.
+ *
+ * Errors: every function returns a ctp_status; nothing throws across the ABI.  Argument and
+ * geometry errors are detected before any device work and leave outputs untouched.
+ * ctp_last_error() gives a thread-local description of the last failure.
+ *
+ * Threading: a plan is immutable after creation and may be used concurrently from several
+ * host threads and streams, provided each concurrent call has its own workspace.
+ */
+#ifndef CTPROJ_H
+#define CTPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTP_OK = 0,
+    CTP_EINVAL = -1,        /* bad argument, size or geometry (e.g. object at/behind source) */
+    CTP_EUNSUPPORTED = -2,  /* valid request that this build does not implement */
+    CTP_ENOMEM = -3,        /* device or host allocation failed */
+    CTP_EDEVICE = -4        /* HIP runtime / launch failure */
+} ctp_status;
+
+/* Scan kinds (Section 2.2). */
+typedef enum { CTP_FAN2D = 0, CTP_CONE_CIRC = 1, CTP_CONE_NONCIRC = 2 } ctp_geom_kind;
+/* Detector models (Section 1 and 2.3: curved detectors for 2D fan and 3D circular scans). */
+typedef enum { CTP_DET_FLAT = 0, CTP_DET_CURVED = 1 } ctp_det;
+/* Projector models (Section 2.3). */
+typedef enum { CTP_SF = 0, CTP_DD = 1 } ctp_method;
+/* Storage types; only CTP_F32 is implemented. */
+typedef enum { CTP_F32 = 0, CTP_BF16 = 1, CTP_F16 = 2 } ctp_dtype;
+/* Direction of a call, for workspace queries. */
+typedef enum { CTP_FORWARD = 0, CTP_BACKWARD = 1 } ctp_direction;
+
+/*
+ * Geometry descriptor (Section 2.2, Table 1).  Each per-view parameter is a host pointer to
+ * either one double (len == 1: every view shares it) or n_views doubles (len == n_views:
+ * one value per view); a NULL pointer with len 0 means 0.0.  Angles in radians, lengths in
+ * mm.  For CTP_FAN2D set nz = nv = 1 (dz, dv, z_src, z_ofst, v_ofst, phi, psi are ignored).
+ * phi and psi must be zero unless kind == CTP_CONE_NONCIRC.  The descriptor is read only
+ * during ctp_plan_create.
+ */
+typedef struct {
+    ctp_geom_kind kind;
+    ctp_det det;
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+    int32_t nu, nv;
+    double du, dv;
+    int32_t n_views;
+    const double *theta, *phi, *psi, *sad, *sdd, *x_src, *z_src,
+                 *x_ofst, *y_ofst, *z_ofst, *u_ofst, *v_ofst;
+    int32_t len_theta, len_phi, len_psi, len_sad, len_sdd, len_x_src, len_z_src,
+            len_x_ofst, len_y_ofst, len_z_ofst, len_u_ofst, len_v_ofst;
+} ctp_geometry_desc;
+
+typedef struct ctp_plan ctp_plan;   /* opaque; immutable after creation */
+
+/*
+ * Expand the geometry per view in FP64 on the host (source, detector frame, projection
+ * constants, DD driving axis), validate it, and upload the per-view table to the current
+ * HIP device.  The plan is bound to that device.
+ * Errors: CTP_EINVAL for non-positive sizes or spacings, a len field other than 0, 1 or
+ * n_views, a NULL pointer with a non-zero len, any corner of the volume at or behind the
+ * source plane in some view, or (DD) a detector column ray parallel to the driving planes;
+ * CTP_EUNSUPPORTED for a curved detector with a non-circular scan (Section 2.3), a curved
+ * detector with a non-zero x_src, DD with a non-circular scan, or a footprint wider than 16
+ * detector columns; CTP_ENOMEM / CTP_EDEVICE for allocation / upload failures.
+ * On success *out owns a device table of 128 bytes per view.
+ */
+ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_plan **out);
+
+/* Free the plan's device table.  The caller must ensure no call using it is in flight.
+ * NULL is accepted. */
+ctp_status ctp_plan_destroy(ctp_plan *plan);
+
+/* Bytes of one volume and one sinogram for `batch` items in dtype (FP32 only). */
+ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch,
+                          size_t *vol_bytes, size_t *sino_bytes);
+
+/* Device workspace (bytes) that ctp_project / ctp_backproject need for `batch` items:
+ * forward: one transposed copy of the volume (z fastest); backward: one copy of the
+ * sinogram scaled by the per-cell amplitude.  May be 0 (2D SF backward needs none). */
+ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t batch,
+                               size_t *bytes);
+
+/*
+ * Forward projection (Eq. 1): sino = A vol, or sino += A vol when accumulate != 0.
+ * vol, sino: device pointers in the layouts above, `batch` items (batch >= 1; the plan is
+ * shared by all items, Section 1: batched, channelled tensors).  workspace: device pointer
+ * of at least ctp_workspace_bytes(plan, CTP_FORWARD, batch) bytes, owned by the caller and
+ * not used by any other concurrent call; 256-byte alignment required.  Asynchronous on
+ * `stream` (0 = null stream); returns after enqueueing.
+ * Errors: CTP_EINVAL (NULL pointers, batch < 1, workspace too small or misaligned, plan used
+ * on another device), CTP_EUNSUPPORTED (dtype other than CTP_F32), CTP_EDEVICE (launch).
+ */
+ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype,
+                       void *sino, ctp_dtype sino_dtype, int64_t batch, int accumulate,
+                       void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Back projection (Eq. 2), the exact transpose of ctp_project with the same weights:
+ * vol = A^T sino, or vol += A^T sino when accumulate != 0.  Arguments as for ctp_project,
+ * with the workspace sized by ctp_workspace_bytes(plan, CTP_BACKWARD, batch).
+ */
+ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype,
+                           void *vol, ctp_dtype vol_dtype, int64_t batch, int accumulate,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Static description of a status code. */
+const char *ctp_status_string(ctp_status status);
+
+/* Thread-local detail message of the last failing call on this thread ("" if none). */
+const char *ctp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTPROJ_H */

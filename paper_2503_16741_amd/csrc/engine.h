@@ -1,0 +1,82 @@
+// engine.h -- internal types shared by the host plan (plan.cpp) and the kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ctp {
+
+enum Geom : int { kFan2D = 0, kCirc = 1, kNonCirc = 2 };
+enum Det : int { kFlat = 0, kCurved = 1 };
+enum Method : int { kSF = 0, kDD = 1 };
+
+constexpr int kStripW = 16;      // detector columns owned by one forward work-group
+constexpr int kMaxCells = 16;    // widest supported transaxial footprint (columns)
+constexpr int kRowsMax = 512;    // detector rows (or 2D batch items) held in LDS at once
+constexpr int kZChunk = 16;      // voxels per lane along z in the back projector
+constexpr int kTile = 8;         // 8 x 8 voxel columns per wavefront tile
+
+// Per-view constants, object-centred coordinates (the object offset is folded into the
+// source and detector), FP32.  Built in FP64 on the host.  128 bytes.
+struct alignas(16) ViewRec {
+    float eu[3];    // detector u axis
+    float ev[3];    // detector v axis
+    float n[3];     // detector normal (towards the source)
+    float s[3];     // source position
+    float dms[3];   // detector reference point minus source
+    float seu;      // s . eu
+    float sev;      // s . ev
+    float sn;       // s . n
+    float Du;       // flat: ((s-d).n)/du      curved: SDD/du
+    float Dv;       // flat: ((s-d).n)/dv      curved: SDD/dv
+    float cu;       // flat: ((s-d).eu - ue0)/du   curved: -ue0/du   (column units)
+    float cv;       // ((s-d).ev - ve0)/dv                           (row units)
+    float ue0;      // detector u of the first column edge (mm)
+    float ve0;      // detector v of the first row edge (mm)
+    float sdd;      // SDD (mm)
+    float sd_ev;    // (s-d).ev (mm)
+    int ydrv;       // DD: 1 = planes y = const, 0 = planes x = const
+    float ddC;      // DD axial constant: -((d-s).z + ve0)/dv (row units)
+    float pad[4];
+};
+static_assert(sizeof(ViewRec) == 128, "ViewRec must stay 128 bytes");
+
+// Launch-time constants shared by all kernels.
+struct Params {
+    int nx, ny, nz;          // volume; for 2D nz = number of batch items (see below)
+    float dx, dy, dz;
+    float x0, y0, z0;        // centre of voxel 0 along each axis (object-centred)
+    int nu, nv;              // detector; for 2D nv = number of batch items
+    float du, dv;
+    int n_views;
+    // Addressing.  For 3D "z" is the slice and "row" the detector row; for 2D both are the
+    // batch item (the batch is processed as the axial dimension, weight 1).
+    int64_t vol_z_stride;    // elements between consecutive z in the user volume
+    int64_t vol_b_stride;    // elements between batch items in the user volume (3D)
+    int64_t sino_row_stride; // elements between consecutive rows
+    int64_t sino_view_stride;
+    int64_t sino_b_stride;   // elements between batch items (3D)
+    float eps;               // ramps narrower than this (cells) are steps
+};
+
+// Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.
+struct LaunchCfg {
+    int geom, det, method, kcells;
+    int n_strips, n_row_chunks;
+};
+
+hipError_t launch_transpose_zfast(const float *vol, float *volT, int64_t batch, int64_t nz,
+                                  int64_t plane, hipStream_t st);
+hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                            const float *sino, float *out, int64_t batch, hipStream_t st);
+hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                          const float *volT, float *sino, int64_t batch, int accumulate,
+                          hipStream_t st);
+hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                           const float *ysc, float *vol, int64_t batch, int accumulate,
+                           hipStream_t st);
+
+}  // namespace ctp

@@ -1,0 +1,982 @@
+// kernels.hip -- gfx950 kernels of the SF / DD projector pair (paper, Section 2.3).
+//
+// Forward (y = A x, Eq. 1) is output-stationary: a work-group owns one view and a strip of
+// kStripW detector columns, accumulates every row of that strip in LDS, and walks only the
+// voxel columns whose transaxial footprint meets the strip (tile culling, then per-column
+// test).  Inside a wavefront the lanes run along z of one voxel column, so the column's
+// transaxial footprint is computed once and broadcast, the axial footprints of neighbouring
+// lanes land in different detector rows (few LDS-atomic collisions), and the volume, read
+// from a z-fastest copy, is read with unit stride.  Each strip is written once: no global
+// atomics.
+//
+// Back projection (x = A^T y, Eq. 2) is voxel-stationary: each lane owns one voxel column
+// and kZChunk voxels along z, loops over all views and gathers the sinogram cells its
+// footprint touches (the 64 lanes of a wavefront are an 8 x 8 column tile, so their reads hit
+// a few neighbouring cache lines); each voxel is written once.  It reads a copy of the
+// sinogram pre-multiplied by the per-cell amplitude, which is the transpose of the forward
+// pass's final per-cell scaling.
+//
+// Both directions call the same device functions for the footprint weights, so the pair is
+// matched up to the order of the FP32 sums.
+#include "engine.h"
+
+#include <hip/hip_runtime.h>
+
+namespace ctp {
+namespace {
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float readlane_f(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int readlane_i(int v, int lane)
+{
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+__device__ __forceinline__ void sort4(float &a, float &b, float &c, float &d)
+{
+    float t;
+    t = fminf(a, b); b = fmaxf(a, b); a = t;
+    t = fminf(c, d); d = fmaxf(c, d); c = t;
+    t = fminf(a, c); c = fmaxf(a, c); a = t;
+    t = fminf(b, d); d = fmaxf(b, d); b = t;
+    t = fminf(b, c); c = fmaxf(b, c); b = t;
+}
+
+// Antiderivative of the unit-height trapezoid with corners k0 <= k1 <= k2 <= k3, in detector
+// cell units (cell edges are the integers).  Ramps narrower than eps are steps.
+struct Trap {
+    float k0, k1, k2, k3;
+    float r1, rp, r2;   // rising ramp, plateau, falling ramp widths (ramps zeroed if steps)
+    float h1, h2;       // 1/(2 r1), 1/(2 r2), or 0 for steps
+    float area;         // G(+inf)
+};
+
+__device__ __forceinline__ Trap make_trap(float k0, float k1, float k2, float k3, float eps)
+{
+    Trap t;
+    const float r1 = k1 - k0, r2 = k3 - k2;
+    const bool s1 = r1 > eps, s2 = r2 > eps;
+    t.k0 = k0;
+    t.k1 = k1;
+    t.k2 = k2;
+    t.k3 = k3;
+    t.r1 = s1 ? r1 : 0.0f;
+    t.r2 = s2 ? r2 : 0.0f;
+    t.rp = k2 - k1;
+    t.h1 = s1 ? 0.5f * fast_rcp(r1) : 0.0f;
+    t.h2 = s2 ? 0.5f * fast_rcp(r2) : 0.0f;
+    t.area = 0.5f * t.r1 + t.rp + 0.5f * t.r2;
+    return t;
+}
+
+__device__ __forceinline__ float trap_G(const Trap &t, float x)
+{
+    const float s1 = fminf(fmaxf(x - t.k0, 0.0f), t.r1);
+    const float sp = fminf(fmaxf(x - t.k1, 0.0f), t.rp);
+    const float s2 = fminf(fmaxf(x - t.k2, 0.0f), t.r2);
+    return fmaf(s1 * s1, t.h1, sp) + fmaf(-s2 * t.h2, s2, s2);
+}
+
+// ---- transaxial footprint of a voxel column (circular scans: independent of z) ----------
+
+// SF: u-projections of the four transaxial corners, sorted, relative to the integer column
+// origin o; the amplitude l_phi0; and the axial magnification (rows per mm of z - z_src) at
+// the nearest and farthest corner, which bound the axial footprint's corners (SF-TT).
+struct SFCol {
+    int o;
+    float t0, t1, t2, t3;
+    float amp;
+    float An, Af;
+};
+
+template <int DET>
+__device__ __forceinline__ void sf_column(const ViewRec &V, const Params &P, float xc, float yc,
+                                          float zc, SFCol &c)
+{
+    const float hx = 0.5f * P.dx, hy = 0.5f * P.dy;
+    // (p - s).eu and (s - p).n at the column centre (zc only matters for tilted poses)
+    const float ac = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], fmaf(zc, V.eu[2], -V.seu)));
+    const float Wc = V.sn - fmaf(xc, V.n[0], fmaf(yc, V.n[1], zc * V.n[2]));
+    const float ax = hx * V.eu[0], ay = hy * V.eu[1];
+    const float wx = -hx * V.n[0], wy = -hy * V.n[1];
+    const float da[4] = {-ax - ay, ax - ay, -ax + ay, ax + ay};
+    const float dW[4] = {-wx - wy, wx - wy, -wx + wy, wx + wy};
+    float t[4], mn = 3.0e38f, mx = 0.0f, uc;
+    if (DET == kFlat) {
+        uc = fmaf(V.Du, ac / Wc, V.cu);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float Wk = Wc + dW[k];
+            // u_k - u_c without cancellation: Du (da W_c - a_c dW) / (W_k W_c)
+            t[k] = V.Du * (fmaf(da[k], Wc, -ac * dW[k]) / (Wk * Wc));
+            mn = fminf(mn, Wk);
+            mx = fmaxf(mx, Wk);
+        }
+    } else {
+        uc = fmaf(V.Du, atan2f(ac, Wc), V.cu);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float ak = ac + da[k], Wk = Wc + dW[k];
+            // angle difference atan2(a_k, W_k) - atan2(a_c, W_c)
+            t[k] = V.Du * atan2f(fmaf(da[k], Wc, -ac * dW[k]), fmaf(Wk, Wc, ak * ac));
+            const float rho = sqrtf(fmaf(ak, ak, Wk * Wk));
+            mn = fminf(mn, rho);
+            mx = fmaxf(mx, rho);
+        }
+    }
+    const float of = floorf(fminf(fmaxf(uc, -1.0e7f), 1.0e7f));
+    const float base = uc - of;
+    c.o = (int)of;
+    c.t0 = t[0] + base;
+    c.t1 = t[1] + base;
+    c.t2 = t[2] + base;
+    c.t3 = t[3] + base;
+    sort4(c.t0, c.t1, c.t2, c.t3);
+    c.An = V.Dv / mn;
+    c.Af = V.Dv / mx;
+    const float gx = xc - V.s[0], gy = yc - V.s[1];
+    const float g = sqrtf(fmaf(gx, gx, gy * gy));
+    c.amp = g * fminf(P.dx / fabsf(gx), P.dy / fabsf(gy));
+}
+
+// Cell weights amp * F1 for K consecutive columns starting at absolute column cs.
+template <int K>
+__device__ __forceinline__ void sf_cell_weights(const SFCol &c, int cs, int nc, float eps,
+                                                float (&w)[K])
+{
+    const Trap tr = make_trap(c.t0, c.t1, c.t2, c.t3, eps);
+    const float x0 = (float)(cs - c.o);
+    float gprev = trap_G(tr, x0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float g = trap_G(tr, x0 + (float)(k + 1));
+        w[k] = k < nc ? c.amp * (g - gprev) : 0.0f;
+        gprev = g;
+    }
+}
+
+// DD: columns touched by the voxel's in-plane interval on its driving plane, the fraction of
+// each mapped column covered, and the axial map scale (rows per mm) along each column's
+// centre ray.
+template <int DET>
+__device__ __forceinline__ float dd_detector_u(const ViewRec &V, float a, float W)
+{
+    return DET == kFlat ? fmaf(V.Du, a / W, V.cu) : fmaf(V.Du, atan2f(a, W), V.cu);
+}
+
+template <int DET>
+__device__ __forceinline__ void dd_ray_xy(const ViewRec &V, float umm, float &qx, float &qy)
+{
+    if (DET == kFlat) {
+        qx = fmaf(umm, V.eu[0], V.dms[0]);
+        qy = fmaf(umm, V.eu[1], V.dms[1]);
+    } else {
+        float sg, cg;
+        sincosf(umm / V.sdd, &sg, &cg);
+        qx = V.sdd * (sg * V.eu[0] - cg * V.n[0]);
+        qy = V.sdd * (sg * V.eu[1] - cg * V.n[1]);
+    }
+}
+
+template <int DET>
+__device__ __forceinline__ void dd_column_range(const ViewRec &V, const Params &P, float xc,
+                                                float yc, int &cmin, int &cmax)
+{
+    float pax, pay, pbx, pby;
+    if (V.ydrv) {
+        pax = xc - 0.5f * P.dx; pbx = xc + 0.5f * P.dx; pay = pby = yc;
+    } else {
+        pay = yc - 0.5f * P.dy; pby = yc + 0.5f * P.dy; pax = pbx = xc;
+    }
+    const float aa = fmaf(pax, V.eu[0], fmaf(pay, V.eu[1], -V.seu));
+    const float Wa = V.sn - fmaf(pax, V.n[0], pay * V.n[1]);
+    const float ab = fmaf(pbx, V.eu[0], fmaf(pby, V.eu[1], -V.seu));
+    const float Wb = V.sn - fmaf(pbx, V.n[0], pby * V.n[1]);
+    const float ua = dd_detector_u<DET>(V, aa, Wa), ub = dd_detector_u<DET>(V, ab, Wb);
+    cmin = (int)floorf(fminf(fmaxf(fminf(ua, ub), -1.0e7f), 1.0e7f));
+    cmax = (int)floorf(fminf(fmaxf(fmaxf(ua, ub), -1.0e7f), 1.0e7f));
+}
+
+template <int DET, int K>
+__device__ __forceinline__ void dd_cell_weights(const ViewRec &V, const Params &P, float xc,
+                                                float yc, int cs, int nc, float (&fx)[K],
+                                                float (&bz)[K])
+{
+    const bool yd = V.ydrv != 0;
+    const float plane = yd ? yc : xc;
+    const float sa = yd ? V.s[1] : V.s[0], sb = yd ? V.s[0] : V.s[1];
+    const float lo = yd ? xc - 0.5f * P.dx : yc - 0.5f * P.dy;
+    const float hi = yd ? xc + 0.5f * P.dx : yc + 0.5f * P.dy;
+    const float dist = plane - sa;
+    float qx, qy;
+    dd_ray_xy<DET>(V, fmaf((float)cs, P.du, V.ue0), qx, qy);
+    float Xprev = fmaf(dist, (yd ? qx : qy) / (yd ? qy : qx), sb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        dd_ray_xy<DET>(V, fmaf((float)(cs + k + 1), P.du, V.ue0), qx, qy);
+        const float X = fmaf(dist, (yd ? qx : qy) / (yd ? qy : qx), sb);
+        const float mlo = fminf(X, Xprev), mhi = fmaxf(X, Xprev);
+        const float ov = fminf(hi, mhi) - fmaxf(lo, mlo);
+        fx[k] = (k < nc && ov > 0.0f) ? ov / (mhi - mlo) : 0.0f;
+        Xprev = X;
+        dd_ray_xy<DET>(V, fmaf((float)cs + (float)k + 0.5f, P.du, V.ue0), qx, qy);
+        bz[k] = (yd ? qy : qx) / (dist * P.dv);
+    }
+}
+
+// ---- per-cell amplitude (applied after the forward sum / before the adjoint gather) ------
+
+template <int GEOM, int DET, int METHOD>
+__device__ __forceinline__ float cell_amp(const ViewRec &V, const Params &P, int i, int j)
+{
+    if (GEOM == kFan2D && METHOD == kSF)
+        return 1.0f;
+    const float u = fmaf((float)i + 0.5f, P.du, V.ue0);
+    const float v = GEOM == kFan2D ? 0.0f : fmaf((float)j + 0.5f, P.dv, V.ve0);
+    float rx, ry, rz;
+    if (DET == kFlat) {
+        rx = fmaf(u, V.eu[0], fmaf(v, V.ev[0], V.dms[0]));
+        ry = fmaf(u, V.eu[1], fmaf(v, V.ev[1], V.dms[1]));
+        rz = fmaf(u, V.eu[2], fmaf(v, V.ev[2], V.dms[2]));
+    } else {
+        float sg, cg;
+        sincosf(u / V.sdd, &sg, &cg);
+        const float h = GEOM == kFan2D ? 0.0f : v - V.sd_ev;
+        rx = fmaf(V.sdd, sg * V.eu[0] - cg * V.n[0], h * V.ev[0]);
+        ry = fmaf(V.sdd, sg * V.eu[1] - cg * V.n[1], h * V.ev[1]);
+        rz = fmaf(V.sdd, sg * V.eu[2] - cg * V.n[2], h * V.ev[2]);
+    }
+    if (GEOM == kFan2D)
+        rz = 0.0f;
+    const float r = sqrtf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+    if (METHOD == kSF)
+        return r / sqrtf(fmaf(rx, rx, ry * ry));
+    return V.ydrv ? P.dy * r / fabsf(ry) : P.dx * r / fabsf(rx);
+}
+
+// ---- SF axial footprint of one voxel (circular scans) -----------------------------------
+
+// Rows are relative to the caller's row origin; `an`, `bn`, `af`, `bf` give the v-projection
+// (rows) of the voxel's bottom face at the nearest / farthest corner as a + b * z; the top
+// face is one slice higher.
+__device__ __forceinline__ Trap sf_axial(float an, float bn, float af, float bf, float z,
+                                         float eps)
+{
+    const float vbn = fmaf(bn, z, an), vbf = fmaf(bf, z, af);
+    const float vtn = vbn + bn, vtf = vbf + bf;
+    const float k0 = fminf(vbn, vbf), k3 = fmaxf(vtn, vtf);
+    const float m1 = fmaxf(vbn, vbf), m2 = fminf(vtn, vtf);
+    return make_trap(k0, fminf(m1, m2), fmaxf(m1, m2), k3, eps);
+}
+
+// Visit the rows of trapezoid tr that lie in [0, R): fn(j, F_j) with F_j = G(j+1) - G(j).
+// The loop is bounded by R whatever the trapezoid's position.
+template <typename Fn>
+__device__ __forceinline__ void for_rows(const Trap &tr, int R, Fn &&fn)
+{
+    const float fr = (float)R;
+    const int j0 = (int)floorf(fminf(fmaxf(tr.k0, -1.0f), fr));
+    const int j1 = (int)floorf(fminf(fmaxf(tr.k3, -1.0f), fr));
+    const int js = max(j0, 0), je = min(j1, R - 1);
+    float gprev = js > j0 ? trap_G(tr, (float)js) : 0.0f;
+    for (int j = js; j <= je; ++j) {
+        const float g = j < j1 ? trap_G(tr, (float)(j + 1)) : tr.area;
+        fn(j, g - gprev);
+        gprev = g;
+    }
+}
+
+// DD axial overlap: rows j in [0, R) met by the mapped voxel interval [zl, zh] (row units);
+// fn(j, overlap).
+template <typename Fn>
+__device__ __forceinline__ void for_dd_rows(float zl, float zh, int R, Fn &&fn)
+{
+    const float fr = (float)R;
+    const int js = max((int)floorf(fminf(fmaxf(zl, -1.0f), fr)), 0);
+    const int je = min((int)floorf(fminf(fmaxf(zh, -1.0f), fr)), R - 1);
+    for (int j = js; j <= je; ++j) {
+        const float wz = fminf(zh, (float)(j + 1)) - fmaxf(zl, (float)j);
+        if (wz > 0.0f)
+            fn(j, wz);
+    }
+}
+
+// SF footprint of one voxel for non-circular poses (flat detector): everything per voxel.
+struct SFVox {
+    int o;              // column origin
+    float t0, t1, t2, t3;
+    Trap ax;            // axial trapezoid in rows relative to the row origin
+};
+
+__device__ __forceinline__ void sf_voxel_noncirc(const ViewRec &V, const Params &P, float xc,
+                                                 float yc, float zc, float row0, SFVox &r)
+{
+    const float hx = 0.5f * P.dx, hy = 0.5f * P.dy, hz = 0.5f * P.dz;
+    const float ac = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], fmaf(zc, V.eu[2], -V.seu)));
+    const float Wc = V.sn - fmaf(xc, V.n[0], fmaf(yc, V.n[1], zc * V.n[2]));
+    const float ax = hx * V.eu[0], ay = hy * V.eu[1];
+    const float wx = -hx * V.n[0], wy = -hy * V.n[1];
+    const float da[4] = {-ax - ay, ax - ay, -ax + ay, ax + ay};
+    const float dW[4] = {-wx - wy, wx - wy, -wx + wy, wx + wy};
+    const float iWc = fast_rcp(Wc);
+    const float uc = fmaf(V.Du * ac, iWc, V.cu);
+    float t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float Wk = Wc + dW[k];
+        t[k] = V.Du * fmaf(da[k], Wc, -ac * dW[k]) * fast_rcp(Wk * Wc);
+    }
+    const float of = floorf(fminf(fmaxf(uc, -1.0e7f), 1.0e7f)), base = uc - of;
+    r.o = (int)of;
+    r.t0 = t[0] + base;
+    r.t1 = t[1] + base;
+    r.t2 = t[2] + base;
+    r.t3 = t[3] + base;
+    sort4(r.t0, r.t1, r.t2, r.t3);
+    // axial: v of the four bottom and four top corners
+    const float hc = fmaf(xc, V.ev[0], fmaf(yc, V.ev[1], fmaf(zc, V.ev[2], -V.sev)));
+    const float ex = hx * V.ev[0], ey = hy * V.ev[1], ez = hz * V.ev[2];
+    const float nzh = hz * V.n[2];
+    const float dh[4] = {-ex - ey, ex - ey, -ex + ey, ex + ey};
+    float bmn = 3.0e38f, bmx = -3.0e38f, tmn = 3.0e38f, tmx = -3.0e38f;
+    const float cvr = V.cv - row0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float hb = hc + dh[k] - ez, ht = hc + dh[k] + ez;
+        const float Wb = Wc + dW[k] + nzh, Wt = Wc + dW[k] - nzh;
+        const float vb = fmaf(V.Dv * hb, fast_rcp(Wb), cvr);
+        const float vt = fmaf(V.Dv * ht, fast_rcp(Wt), cvr);
+        bmn = fminf(bmn, vb);
+        bmx = fmaxf(bmx, vb);
+        tmn = fminf(tmn, vt);
+        tmx = fmaxf(tmx, vt);
+    }
+    float k0 = bmn, k1 = bmx, k2 = tmn, k3 = tmx;
+    sort4(k0, k1, k2, k3);
+    r.ax = make_trap(k0, k1, k2, k3, P.eps);
+}
+
+__device__ __forceinline__ float sf_amp(const ViewRec &V, const Params &P, float xc, float yc)
+{
+    const float gx = xc - V.s[0], gy = yc - V.s[1];
+    const float g = sqrtf(fmaf(gx, gx, gy * gy));
+    return g * fminf(P.dx / fabsf(gx), P.dy / fabsf(gy));
+}
+
+// ---- tile culling --------------------------------------------------------------------------
+
+// Detector column range (absolute, cells) that the xy-box [x0,x1] x [y0,y1] (all z) can
+// reach.  The projection of a box lies inside the hull of its projected corners.
+template <int GEOM, int DET>
+__device__ __forceinline__ void box_u_range(const ViewRec &V, const Params &P, float bx0,
+                                            float bx1, float by0, float by1, float &umin,
+                                            float &umax)
+{
+    umin = 3.0e38f;
+    umax = -3.0e38f;
+    const int nzc = GEOM == kNonCirc ? 2 : 1;
+    const float zlo = P.z0 - 0.5f * P.dz, zhi = P.z0 + ((float)P.nz - 0.5f) * P.dz;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float x = (k & 1) ? bx1 : bx0, y = (k & 2) ? by1 : by0;
+        for (int q = 0; q < nzc; ++q) {
+            const float z = GEOM == kNonCirc ? (q ? zhi : zlo) : 0.0f;
+            const float a = fmaf(x, V.eu[0], fmaf(y, V.eu[1], fmaf(z, V.eu[2], -V.seu)));
+            const float W = V.sn - fmaf(x, V.n[0], fmaf(y, V.n[1], z * V.n[2]));
+            const float u = DET == kFlat ? fmaf(V.Du, a / W, V.cu) : fmaf(V.Du, atan2f(a, W), V.cu);
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+        }
+    }
+}
+
+constexpr int kListCap = 2048;
+
+// ============================================================================================
+// Forward projector
+// ============================================================================================
+template <int GEOM, int DET, int METHOD, int K>
+__global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
+                                                  const float *__restrict__ volT,
+                                                  float *__restrict__ sino, int accumulate,
+                                                  int n_row_chunks)
+{
+    extern __shared__ float acc[];           // [R][kStripW + 1]
+    __shared__ int s_count;
+    __shared__ unsigned short s_list[kListCap];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int strip = blockIdx.x, view = blockIdx.y;
+    const int chunk = blockIdx.z % n_row_chunks;
+    const int b = blockIdx.z / n_row_chunks;            // batch item (3D); 0 in 2D
+    const int i_lo = strip * kStripW;
+    const int i_hi = min(i_lo + kStripW, P.nu);
+    const int rows_total = GEOM == kFan2D ? P.nz : P.nv;
+    const int r0 = chunk * kRowsMax;
+    const int R = min(kRowsMax, rows_total - r0);
+    const ViewRec V = views[view];
+    constexpr int SW = kStripW + 1;
+
+    for (int e = threadIdx.x; e < R * SW; e += blockDim.x)
+        acc[e] = 0.0f;
+
+    const float hz = 0.5f * P.dz;
+    const float zb0 = P.z0 - hz - V.s[2];               // bottom face of slice 0, minus z_src
+    const int tiles_x = (P.nx + kTile - 1) / kTile;
+    const int tiles_y = (P.ny + kTile - 1) / kTile;
+    const int ntiles = tiles_x * tiles_y;
+    // voxel "z" run handled by the lanes: slices (3D) or batch items in this chunk (2D)
+    const int zbeg = GEOM == kFan2D ? r0 : 0;
+    const int zend = GEOM == kFan2D ? r0 + R : P.nz;
+    const float ulo = (float)i_lo - 1e-3f, uhi = (float)i_hi + 1e-3f;
+    const int64_t colstride = P.nz;      // z-fastest copy: one voxel column is contiguous
+    const float *volb = volT + (GEOM == kFan2D ? 0 : (int64_t)b * P.nx * P.ny * P.nz);
+
+    for (int t0 = 0; t0 < ntiles; t0 += kListCap) {
+        const int tend = min(t0 + kListCap, ntiles);
+        if (threadIdx.x == 0)
+            s_count = 0;
+        __syncthreads();
+        for (int tt = t0 + wave * 64; tt < tend; tt += 256) {
+            const int t = tt + lane;
+            bool hit = false;
+            if (t < tend) {
+                const int tx = t % tiles_x, ty = t / tiles_x;
+                const float bx0 = P.x0 + ((float)(tx * kTile) - 0.5f) * P.dx;
+                const float bx1 = P.x0 + ((float)min(tx * kTile + kTile, P.nx) - 0.5f) * P.dx;
+                const float by0 = P.y0 + ((float)(ty * kTile) - 0.5f) * P.dy;
+                const float by1 = P.y0 + ((float)min(ty * kTile + kTile, P.ny) - 0.5f) * P.dy;
+                float umin, umax;
+                box_u_range<GEOM, DET>(V, P, bx0, bx1, by0, by1, umin, umax);
+                hit = umax >= ulo && umin <= uhi;
+            }
+            const uint64_t m = __ballot(hit);
+            const int pre = __popcll(m & ((1ull << lane) - 1ull));
+            int base = 0;
+            if (lane == 0 && m)
+                base = atomicAdd(&s_count, (int)__popcll(m));
+            base = __shfl(base, 0);
+            if (hit)
+                s_list[base + pre] = (unsigned short)(t - t0);
+        }
+        __syncthreads();
+        const int nhit = s_count;
+
+        for (int h = wave; h < nhit; h += 4) {
+            const int t = t0 + s_list[h];
+            const int tx = t % tiles_x, ty = t / tiles_x;
+            const int ix = tx * kTile + (lane & (kTile - 1));
+            const int iy = ty * kTile + (lane >> 3);
+            const bool valid = ix < P.nx && iy < P.ny;
+            const float xc = fmaf((float)ix, P.dx, P.x0), yc = fmaf((float)iy, P.dy, P.y0);
+
+            if constexpr (METHOD == kSF && GEOM != kNonCirc) {
+                SFCol col;
+                sf_column<DET>(V, P, xc, yc, 0.0f, col);
+                const int cmin = col.o + (int)floorf(col.t0), cmax = col.o + (int)floorf(col.t3);
+                const int cs = max(cmin, i_lo), ce = min(cmax, i_hi - 1);
+                const int nc = valid ? max(ce - cs + 1, 0) : 0;
+                float w[K];
+                sf_cell_weights<K>(col, cs, nc, P.eps, w);
+                const float an = fmaf(col.An, zb0, V.cv - (float)r0), bn = col.An * P.dz;
+                const float af = fmaf(col.Af, zb0, V.cv - (float)r0), bf = col.Af * P.dz;
+                uint64_t m = __ballot(nc > 0);
+                while (m) {
+                    const int c = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1ull;
+                    const int s_ix = readlane_i(ix, c), s_iy = readlane_i(iy, c);
+                    const int s_nc = readlane_i(nc, c), s_slot = readlane_i(cs, c) - i_lo;
+                    float sw[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        sw[k] = readlane_f(w[k], c);
+                    const float s_an = readlane_f(an, c), s_bn = readlane_f(bn, c);
+                    const float s_af = readlane_f(af, c), s_bf = readlane_f(bf, c);
+                    const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
+                    float *accs = acc + s_slot;
+                    for (int z = zbeg + lane; z < zend; z += 64) {
+                        const float val = colp[z];
+                        if constexpr (GEOM == kFan2D) {
+                            float *a = accs + (z - r0) * SW;
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                if (k < s_nc)
+                                    atomicAdd(a + k, val * sw[k]);
+                        } else {
+                            const Trap tr = sf_axial(s_an, s_bn, s_af, s_bf, (float)z, P.eps);
+                            for_rows(tr, R, [&](int j, float F) {
+                                const float f = F * val;
+                                float *a = accs + j * SW;
+#pragma unroll
+                                for (int k = 0; k < K; ++k)
+                                    if (k < s_nc)
+                                        atomicAdd(a + k, f * sw[k]);
+                            });
+                        }
+                    }
+                }
+            } else if constexpr (METHOD == kSF && GEOM == kNonCirc) {
+                // conservative per-column test over all z, then everything per voxel
+                float umin, umax;
+                box_u_range<GEOM, DET>(V, P, xc - 0.5f * P.dx, xc + 0.5f * P.dx,
+                                       yc - 0.5f * P.dy, yc + 0.5f * P.dy, umin, umax);
+                const bool hit = valid && umax >= ulo && umin <= uhi;
+                const float amp = sf_amp(V, P, xc, yc);
+                uint64_t m = __ballot(hit);
+                while (m) {
+                    const int c = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1ull;
+                    const int s_ix = readlane_i(ix, c), s_iy = readlane_i(iy, c);
+                    const float s_x = readlane_f(xc, c), s_y = readlane_f(yc, c);
+                    const float s_amp = readlane_f(amp, c);
+                    const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
+                    for (int z = lane; z < P.nz; z += 64) {
+                        const float val = colp[z];
+                        SFVox vx;
+                        sf_voxel_noncirc(V, P, s_x, s_y, fmaf((float)z, P.dz, P.z0), (float)r0, vx);
+                        const int cmin = vx.o + (int)floorf(vx.t0), cmax = vx.o + (int)floorf(vx.t3);
+                        const int cs = max(cmin, i_lo), ce = min(cmax, i_hi - 1);
+                        const int nc = max(ce - cs + 1, 0);
+                        if (nc == 0)
+                            continue;
+                        SFCol cc;
+                        cc.o = vx.o; cc.t0 = vx.t0; cc.t1 = vx.t1; cc.t2 = vx.t2; cc.t3 = vx.t3;
+                        cc.amp = s_amp;
+                        float w[K];
+                        sf_cell_weights<K>(cc, cs, nc, P.eps, w);
+                        float *accs = acc + (cs - i_lo);
+                        for_rows(vx.ax, R, [&](int j, float F) {
+                            const float f = F * val;
+                            float *a = accs + j * SW;
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                if (k < nc)
+                                    atomicAdd(a + k, f * w[k]);
+                        });
+                    }
+                }
+            } else {   // DD (2D fan and circular cone)
+                int cmin, cmax;
+                dd_column_range<DET>(V, P, xc, yc, cmin, cmax);
+                const int cs = max(cmin, i_lo), ce = min(cmax, i_hi - 1);
+                const int nc = valid ? max(ce - cs + 1, 0) : 0;
+                float fx[K], bz[K];
+                dd_cell_weights<DET, K>(V, P, xc, yc, cs, nc, fx, bz);
+                uint64_t m = __ballot(nc > 0);
+                while (m) {
+                    const int c = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1ull;
+                    const int s_ix = readlane_i(ix, c), s_iy = readlane_i(iy, c);
+                    const int s_nc = readlane_i(nc, c), s_slot = readlane_i(cs, c) - i_lo;
+                    float sfx[K], sal[K], sbe[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        sfx[k] = readlane_f(fx[k], c);
+                        const float bk = readlane_f(bz[k], c);
+                        sal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
+                        sbe[k] = bk * P.dz;
+                    }
+                    const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
+                    float *accs = acc + s_slot;
+                    for (int z = zbeg + lane; z < zend; z += 64) {
+                        const float val = colp[z];
+                        if constexpr (GEOM == kFan2D) {
+                            float *a = accs + (z - r0) * SW;
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                if (k < s_nc)
+                                    atomicAdd(a + k, val * sfx[k]);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                if (k >= s_nc)
+                                    break;
+                                const float zl = fmaf(sbe[k], (float)z, sal[k]);
+                                const float zh = zl + sbe[k];
+                                const float vk = val * sfx[k];
+                                for_dd_rows(zl, zh, R, [&](int j, float wz) {
+                                    atomicAdd(accs + j * SW + k, vk * wz);
+                                });
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // write the strip, applying the per-cell amplitude
+    for (int e = threadIdx.x; e < R * kStripW; e += blockDim.x) {
+        const int row = e / kStripW, k = e - row * kStripW;
+        const int i = i_lo + k;
+        if (i >= i_hi)
+            continue;
+        const int j = r0 + row;
+        const float val = acc[row * SW + k] * cell_amp<GEOM, DET, METHOD>(V, P, i, j);
+        float *dst = sino + (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
+                     (int64_t)j * P.sino_row_stride + i;
+        *dst = accumulate ? *dst + val : val;
+    }
+}
+
+// ============================================================================================
+// Back projector
+// ============================================================================================
+template <int GEOM, int DET, int METHOD, int K>
+__global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__restrict__ views,
+                                                  const float *__restrict__ ys,
+                                                  float *__restrict__ vol, int accumulate)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles16_x = (P.nx + 15) >> 4;
+    const int T = blockIdx.x;
+    const int ix = (T % tiles16_x) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int iy = (T / tiles16_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int zc0 = blockIdx.y * kZChunk;
+    const int b = blockIdx.z;                 // batch item (3D); 0 in 2D
+    const bool valid = ix < P.nx && iy < P.ny;
+    const float xc = fmaf((float)ix, P.dx, P.x0), yc = fmaf((float)iy, P.dy, P.y0);
+    const float hz = 0.5f * P.dz;
+    const float *ysb = ys + (int64_t)b * P.sino_b_stride;
+    const int nzv = P.nz;
+    const int rows_total = GEOM == kFan2D ? P.nz : P.nv;
+
+    float acc[kZChunk];
+#pragma unroll
+    for (int q = 0; q < kZChunk; ++q)
+        acc[q] = 0.0f;
+
+    if (valid) {
+        for (int view = 0; view < P.n_views; ++view) {
+            const ViewRec &V = views[view];
+            const float *yv = ysb + (int64_t)view * P.sino_view_stride;
+            const float zb0 = P.z0 - hz - V.s[2];
+
+            if constexpr (METHOD == kSF && GEOM != kNonCirc) {
+                SFCol col;
+                sf_column<DET>(V, P, xc, yc, 0.0f, col);
+                const int cmin = col.o + (int)floorf(col.t0), cmax = col.o + (int)floorf(col.t3);
+                const int cs = max(cmin, 0), ce = min(cmax, P.nu - 1);
+                const int nc = ce - cs + 1;
+                if (nc <= 0)
+                    continue;
+                float w[K];
+                sf_cell_weights<K>(col, cs, nc, P.eps, w);
+                const float *yc0 = yv + cs;
+                if constexpr (GEOM == kFan2D) {
+#pragma unroll
+                    for (int q = 0; q < kZChunk; ++q) {
+                        const int z = zc0 + q;
+                        if (z < nzv) {
+                            const float *yr = yc0 + (int64_t)z * P.sino_row_stride;
+                            float s = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                if (k < nc)
+                                    s = fmaf(w[k], yr[k], s);
+                            acc[q] += s;
+                        }
+                    }
+                } else {
+                    const float an = fmaf(col.An, zb0, V.cv), bn = col.An * P.dz;
+                    const float af = fmaf(col.Af, zb0, V.cv), bf = col.Af * P.dz;
+#pragma unroll
+                    for (int q = 0; q < kZChunk; ++q) {
+                        const int z = zc0 + q;
+                        if (z < nzv) {
+                            const Trap tr = sf_axial(an, bn, af, bf, (float)z, P.eps);
+                            float s = 0.0f;
+                            for_rows(tr, rows_total, [&](int j, float F) {
+                                const float *yr = yc0 + (int64_t)j * P.sino_row_stride;
+                                float rs = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < K; ++k)
+                                    if (k < nc)
+                                        rs = fmaf(w[k], yr[k], rs);
+                                s = fmaf(F, rs, s);
+                            });
+                            acc[q] += s;
+                        }
+                    }
+                }
+            } else if constexpr (METHOD == kSF && GEOM == kNonCirc) {
+                const float amp = sf_amp(V, P, xc, yc);
+#pragma unroll
+                for (int q = 0; q < kZChunk; ++q) {
+                    const int z = zc0 + q;
+                    if (z < nzv) {
+                        SFVox vx;
+                        sf_voxel_noncirc(V, P, xc, yc, fmaf((float)z, P.dz, P.z0), 0.0f, vx);
+                        const int cmin = vx.o + (int)floorf(vx.t0), cmax = vx.o + (int)floorf(vx.t3);
+                        const int cs = max(cmin, 0), ce = min(cmax, P.nu - 1);
+                        const int nc = ce - cs + 1;
+                        if (nc > 0) {
+                            SFCol cc;
+                            cc.o = vx.o; cc.t0 = vx.t0; cc.t1 = vx.t1; cc.t2 = vx.t2; cc.t3 = vx.t3;
+                            cc.amp = amp;
+                            float w[K];
+                            sf_cell_weights<K>(cc, cs, nc, P.eps, w);
+                            float s = 0.0f;
+                            for_rows(vx.ax, rows_total, [&](int j, float F) {
+                                const float *yr = yv + cs + (int64_t)j * P.sino_row_stride;
+                                float rs = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < K; ++k)
+                                    if (k < nc)
+                                        rs = fmaf(w[k], yr[k], rs);
+                                s = fmaf(F, rs, s);
+                            });
+                            acc[q] += s;
+                        }
+                    }
+                }
+            } else {   // DD
+                int cmin, cmax;
+                dd_column_range<DET>(V, P, xc, yc, cmin, cmax);
+                const int cs = max(cmin, 0), ce = min(cmax, P.nu - 1);
+                const int nc = ce - cs + 1;
+                if (nc <= 0)
+                    continue;
+                float fx[K], bz[K];
+                dd_cell_weights<DET, K>(V, P, xc, yc, cs, nc, fx, bz);
+                const float *yc0 = yv + cs;
+                if constexpr (GEOM == kFan2D) {
+#pragma unroll
+                    for (int q = 0; q < kZChunk; ++q) {
+                        const int z = zc0 + q;
+                        if (z < nzv) {
+                            const float *yr = yc0 + (int64_t)z * P.sino_row_stride;
+                            float s = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                if (k < nc)
+                                    s = fmaf(fx[k], yr[k], s);
+                            acc[q] += s;
+                        }
+                    }
+                } else {
+                    float al[K], be[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        al[k] = fmaf(bz[k], zb0, V.ddC);
+                        be[k] = bz[k] * P.dz;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kZChunk; ++q) {
+                        const int z = zc0 + q;
+                        if (z < nzv) {
+                            float s = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                if (k < nc) {
+                                    const float zl = fmaf(be[k], (float)z, al[k]);
+                                    const float zh = zl + be[k];
+                                    float rs = 0.0f;
+                                    for_dd_rows(zl, zh, rows_total, [&](int j, float wz) {
+                                        rs = fmaf(wz, yc0[(int64_t)j * P.sino_row_stride + k], rs);
+                                    });
+                                    s = fmaf(fx[k], rs, s);
+                                }
+                            }
+                            acc[q] += s;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if (valid) {
+        float *vb = vol + (GEOM == kFan2D ? 0 : (int64_t)b * P.vol_b_stride) +
+                    (int64_t)iy * P.nx + ix;
+#pragma unroll
+        for (int q = 0; q < kZChunk; ++q) {
+            const int z = zc0 + q;
+            if (z < nzv) {
+                float *dst = vb + (int64_t)z * P.vol_z_stride;
+                *dst = accumulate ? *dst + acc[q] : acc[q];
+            }
+        }
+    }
+}
+
+// ============================================================================================
+// Helpers: z-fastest copy of the volume, amplitude-scaled copy of the sinogram
+// ============================================================================================
+__global__ __launch_bounds__(256) void transpose_zfast_kernel(const float *__restrict__ in,
+                                                              float *__restrict__ out,
+                                                              int64_t nz, int64_t plane)
+{
+    __shared__ float tile[32][33];
+    const int64_t b = blockIdx.z;
+    const int64_t p0 = (int64_t)blockIdx.x * 32, z0 = (int64_t)blockIdx.y * 32;
+    const float *src = in + b * nz * plane;
+    float *dst = out + b * nz * plane;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t z = z0 + r, p = p0 + tx;
+        if (z < nz && p < plane)
+            tile[r][tx] = src[z * plane + p];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t p = p0 + r, z = z0 + tx;
+        if (z < nz && p < plane)
+            dst[p * nz + z] = tile[tx][r];
+    }
+}
+
+template <int GEOM, int DET, int METHOD>
+__global__ __launch_bounds__(256) void amp_scale_kernel(Params P, const ViewRec *__restrict__ views,
+                                                        const float *__restrict__ in,
+                                                        float *__restrict__ out, int nrows)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int row = blockIdx.y;
+    const int view = blockIdx.z % P.n_views;
+    const int b = blockIdx.z / P.n_views;
+    if (i >= P.nu)
+        return;
+    const int64_t idx = (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
+                        (int64_t)row * P.sino_row_stride + i;
+    out[idx] = in[idx] * cell_amp<GEOM, DET, METHOD>(views[view], P, i, row);
+    (void)nrows;
+}
+
+// ---- dispatch --------------------------------------------------------------------------------
+
+template <int GEOM, int DET, int METHOD, int K>
+hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                      const float *volT, float *sino, int64_t batch, int accumulate,
+                      hipStream_t st)
+{
+    const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
+    const int R = min(kRowsMax, rows_total);
+    const size_t lds = (size_t)R * (kStripW + 1) * sizeof(float);
+    const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
+    dim3 grid(c.n_strips, p.n_views, (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks));
+    hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(256), lds, st, p, views,
+                       volT, sino, accumulate, nchunks);
+    return hipGetLastError();
+}
+
+template <int GEOM, int DET, int METHOD, int K>
+hipError_t bwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                      const float *ysc, float *vol, int64_t batch, int accumulate,
+                      hipStream_t st)
+{
+    (void)c;
+    const int tiles = ((p.nx + 15) / 16) * ((p.ny + 15) / 16);
+    dim3 grid(tiles, (p.nz + kZChunk - 1) / kZChunk, (unsigned)(GEOM == kFan2D ? 1 : batch));
+    hipLaunchKernelGGL((bwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(256), 0, st, p, views,
+                       ysc, vol, accumulate);
+    return hipGetLastError();
+}
+
+template <int GEOM, int DET, int METHOD>
+hipError_t amp_launch(const Params &p, const ViewRec *views, const float *in, float *out,
+                      int64_t batch, hipStream_t st)
+{
+    const int nrows = GEOM == kFan2D ? p.nz : p.nv;
+    dim3 grid((p.nu + 255) / 256, nrows, (unsigned)(p.n_views * (GEOM == kFan2D ? 1 : batch)));
+    hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD>), grid, dim3(256), 0, st, p, views,
+                       in, out, nrows);
+    return hipGetLastError();
+}
+
+// Expand (geom, det, method, K) into a template instance.  Combinations that the plan rejects
+// (non-circular + curved, non-circular + DD) are never instantiated.
+template <template <int, int, int, int> class F, typename... A>
+hipError_t dispatch(const LaunchCfg &c, A &&...a);
+
+#define CTP_FOR_K(G, D, M)                                                              \
+    switch (c.kcells) {                                                                 \
+    case 3: return F<G, D, M, 3>::run(a...);                                            \
+    case 4: return F<G, D, M, 4>::run(a...);                                            \
+    case 8: return F<G, D, M, 8>::run(a...);                                            \
+    default: return F<G, D, M, 16>::run(a...);                                          \
+    }
+
+template <template <int, int, int, int> class F, typename... A>
+hipError_t dispatch(const LaunchCfg &c, A &&...a)
+{
+    if (c.geom == kFan2D && c.det == kFlat && c.method == kSF) { CTP_FOR_K(kFan2D, kFlat, kSF) }
+    if (c.geom == kFan2D && c.det == kCurved && c.method == kSF) { CTP_FOR_K(kFan2D, kCurved, kSF) }
+    if (c.geom == kFan2D && c.det == kFlat && c.method == kDD) { CTP_FOR_K(kFan2D, kFlat, kDD) }
+    if (c.geom == kFan2D && c.det == kCurved && c.method == kDD) { CTP_FOR_K(kFan2D, kCurved, kDD) }
+    if (c.geom == kCirc && c.det == kFlat && c.method == kSF) { CTP_FOR_K(kCirc, kFlat, kSF) }
+    if (c.geom == kCirc && c.det == kCurved && c.method == kSF) { CTP_FOR_K(kCirc, kCurved, kSF) }
+    if (c.geom == kCirc && c.det == kFlat && c.method == kDD) { CTP_FOR_K(kCirc, kFlat, kDD) }
+    if (c.geom == kCirc && c.det == kCurved && c.method == kDD) { CTP_FOR_K(kCirc, kCurved, kDD) }
+    if (c.geom == kNonCirc && c.det == kFlat && c.method == kSF) { CTP_FOR_K(kNonCirc, kFlat, kSF) }
+    return hipErrorInvalidValue;
+}
+#undef CTP_FOR_K
+
+template <int G, int D, int M, int K>
+struct FwdOp {
+    static hipError_t run(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                          const float *volT, float *sino, int64_t batch, int accumulate,
+                          hipStream_t st)
+    {
+        return fwd_launch<G, D, M, K>(p, c, views, volT, sino, batch, accumulate, st);
+    }
+};
+
+template <int G, int D, int M, int K>
+struct BwdOp {
+    static hipError_t run(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                          const float *ysc, float *vol, int64_t batch, int accumulate,
+                          hipStream_t st)
+    {
+        return bwd_launch<G, D, M, K>(p, c, views, ysc, vol, batch, accumulate, st);
+    }
+};
+
+template <int G, int D, int M, int K>
+struct AmpOp {
+    static hipError_t run(const Params &p, const ViewRec *views, const float *in, float *out,
+                          int64_t batch, hipStream_t st)
+    {
+        return amp_launch<G, D, M>(p, views, in, out, batch, st);
+    }
+};
+
+}  // namespace
+
+hipError_t launch_transpose_zfast(const float *vol, float *volT, int64_t batch, int64_t nz,
+                                  int64_t plane, hipStream_t st)
+{
+    dim3 grid((unsigned)((plane + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)batch);
+    hipLaunchKernelGGL(transpose_zfast_kernel, grid, dim3(256), 0, st, vol, volT, nz, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                            const float *sino, float *out, int64_t batch, hipStream_t st)
+{
+    LaunchCfg c4 = c;
+    c4.kcells = 3;
+    return dispatch<AmpOp>(c4, p, views, sino, out, batch, st);
+}
+
+hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                          const float *volT, float *sino, int64_t batch, int accumulate,
+                          hipStream_t st)
+{
+    return dispatch<FwdOp>(c, p, c, views, volT, sino, batch, accumulate, st);
+}
+
+hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,
+                           const float *ysc, float *vol, int64_t batch, int accumulate,
+                           hipStream_t st)
+{
+    return dispatch<BwdOp>(c, p, c, views, ysc, vol, batch, accumulate, st);
+}
+
+}  // namespace ctp

@@ -1,0 +1,477 @@
+// plan.cpp -- host side of the projector library: FP64 geometry expansion (paper, Section 2.2
+// and Table 1), validation, per-view device table, workspace sizing and the C ABI declared in
+// include/ctproj.h.
+#include "engine.h"
+
+#include "../../include/ctproj.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+struct ctp_plan {
+    ctp_geometry_desc g;     // sizes and kinds (pointers cleared)
+    ctp_method method;
+    int device;
+    ctp::ViewRec *d_views;   // device table, n_views records
+    ctp::LaunchCfg cfg;
+    ctp::Params base;        // geometry part of the launch constants
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ctp_status fail(ctp_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+bool sync_debug()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("CTP_SYNC_DEBUG");
+        return e && e[0] && e[0] != '0';
+    }();
+    return on;
+}
+
+struct Vec3 {
+    double x, y, z;
+};
+inline Vec3 operator+(Vec3 a, Vec3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline Vec3 operator-(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline Vec3 operator*(double s, Vec3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(Vec3 a, Vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+struct Mat3 {
+    double m[3][3];
+    Vec3 operator*(Vec3 v) const
+    {
+        return {m[0][0] * v.x + m[0][1] * v.y + m[0][2] * v.z,
+                m[1][0] * v.x + m[1][1] * v.y + m[1][2] * v.z,
+                m[2][0] * v.x + m[2][1] * v.y + m[2][2] * v.z};
+    }
+    Mat3 operator*(const Mat3 &o) const
+    {
+        Mat3 r{};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                r.m[i][j] = m[i][0] * o.m[0][j] + m[i][1] * o.m[1][j] + m[i][2] * o.m[2][j];
+        return r;
+    }
+};
+
+// One view of the scan in world coordinates with the object offset removed.
+struct Frame {
+    Vec3 s, d, eu, ev, n;
+    double sdd, ue0, ve0;     // first column / row edges (absolute detector coordinates)
+};
+
+// Per-view parameter accessor: scalar broadcast or vector.
+struct ParamView {
+    const double *p;
+    int32_t len;
+    double at(int b) const { return p == nullptr ? 0.0 : (len == 1 ? p[0] : p[b]); }
+};
+
+ctp_status check_param(const char *name, const double *p, int32_t len, int32_t n_views)
+{
+    if (p == nullptr && len != 0)
+        return fail(CTP_EINVAL, std::string(name) + ": NULL pointer with non-zero length");
+    if (p != nullptr && len != 1 && len != n_views)
+        return fail(CTP_EINVAL, std::string(name) + ": length must be 1 or n_views");
+    if (p != nullptr)
+        for (int32_t i = 0; i < len; ++i)
+            if (!std::isfinite(p[i]))
+                return fail(CTP_EINVAL, std::string(name) + ": non-finite value");
+    return CTP_OK;
+}
+
+// Pose R = Rz(theta) Rx(phi) Ry(psi): psi about y first, then phi about x, then theta about z,
+// each counter-clockwise (Section 2.2).
+Mat3 pose(double th, double ph, double ps)
+{
+    const double ct = std::cos(th), st = std::sin(th);
+    const double cp = std::cos(ph), sp = std::sin(ph);
+    const double cs = std::cos(ps), ss = std::sin(ps);
+    const Mat3 Rz{{{ct, -st, 0}, {st, ct, 0}, {0, 0, 1}}};
+    const Mat3 Rx{{{1, 0, 0}, {0, cp, -sp}, {0, sp, cp}}};
+    const Mat3 Ry{{{cs, 0, ss}, {0, 1, 0}, {-ss, 0, cs}}};
+    return Rz * (Rx * Ry);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ctp_status_string(ctp_status s)
+{
+    switch (s) {
+    case CTP_OK: return "ok";
+    case CTP_EINVAL: return "invalid argument";
+    case CTP_EUNSUPPORTED: return "unsupported";
+    case CTP_ENOMEM: return "out of memory";
+    case CTP_EDEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char *ctp_last_error(void) { return g_last_error.c_str(); }
+
+ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_plan **out)
+{
+    g_last_error.clear();
+    if (desc == nullptr || out == nullptr)
+        return fail(CTP_EINVAL, "NULL descriptor or output pointer");
+    *out = nullptr;
+    const ctp_geometry_desc &g = *desc;
+    if (g.kind < CTP_FAN2D || g.kind > CTP_CONE_NONCIRC)
+        return fail(CTP_EINVAL, "unknown geometry kind");
+    if (g.det != CTP_DET_FLAT && g.det != CTP_DET_CURVED)
+        return fail(CTP_EINVAL, "unknown detector model");
+    if (method != CTP_SF && method != CTP_DD)
+        return fail(CTP_EINVAL, "unknown projector method");
+    const bool two_d = g.kind == CTP_FAN2D;
+    if (g.nx <= 0 || g.ny <= 0 || g.nu <= 0 || g.n_views <= 0 || (!two_d && (g.nz <= 0 || g.nv <= 0)))
+        return fail(CTP_EINVAL, "sizes must be positive");
+    if (two_d && (g.nz != 1 || g.nv != 1))
+        return fail(CTP_EINVAL, "2D fan beam requires nz = nv = 1");
+    if (!(g.dx > 0) || !(g.dy > 0) || !(g.du > 0) || (!two_d && (!(g.dz > 0) || !(g.dv > 0))))
+        return fail(CTP_EINVAL, "spacings must be positive");
+    if ((int64_t)g.nx * g.ny > (int64_t)1 << 28 || (int64_t)g.nx * g.ny * g.nz > (int64_t)1 << 34)
+        return fail(CTP_EINVAL, "volume too large");
+    if (g.kind == CTP_CONE_NONCIRC && g.det == CTP_DET_CURVED)
+        return fail(CTP_EUNSUPPORTED, "non-circular scans use flat detectors only");
+    if (method == CTP_DD && g.kind == CTP_CONE_NONCIRC)
+        return fail(CTP_EUNSUPPORTED, "distance driven is built for circular scans only");
+
+    struct {
+        const char *name;
+        const double *p;
+        int32_t len;
+    } prm[] = {{"theta", g.theta, g.len_theta}, {"phi", g.phi, g.len_phi}, {"psi", g.psi, g.len_psi},
+               {"sad", g.sad, g.len_sad}, {"sdd", g.sdd, g.len_sdd}, {"x_src", g.x_src, g.len_x_src},
+               {"z_src", g.z_src, g.len_z_src}, {"x_ofst", g.x_ofst, g.len_x_ofst},
+               {"y_ofst", g.y_ofst, g.len_y_ofst}, {"z_ofst", g.z_ofst, g.len_z_ofst},
+               {"u_ofst", g.u_ofst, g.len_u_ofst}, {"v_ofst", g.v_ofst, g.len_v_ofst}};
+    for (auto &q : prm) {
+        ctp_status st = check_param(q.name, q.p, q.len, g.n_views);
+        if (st != CTP_OK)
+            return st;
+    }
+    const ParamView theta{g.theta, g.len_theta}, phi{g.phi, g.len_phi}, psi{g.psi, g.len_psi},
+        sad{g.sad, g.len_sad}, sdd{g.sdd, g.len_sdd}, xsrc{g.x_src, g.len_x_src},
+        zsrc{g.z_src, g.len_z_src}, xo{g.x_ofst, g.len_x_ofst}, yo{g.y_ofst, g.len_y_ofst},
+        zo{g.z_ofst, g.len_z_ofst}, uo{g.u_ofst, g.len_u_ofst}, vo{g.v_ofst, g.len_v_ofst};
+
+    const int nz = two_d ? 1 : g.nz, nv = two_d ? 1 : g.nv;
+    const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dy, hz = two_d ? 0.0 : 0.5 * nz * g.dz;
+    std::vector<ctp::ViewRec> recs((size_t)g.n_views);
+    double kmax = 0.0;   // widest transaxial footprint (columns) over all views
+
+    for (int b = 0; b < g.n_views; ++b) {
+        const double ph = g.kind == CTP_CONE_NONCIRC ? phi.at(b) : 0.0;
+        const double ps = g.kind == CTP_CONE_NONCIRC ? psi.at(b) : 0.0;
+        if (g.kind != CTP_CONE_NONCIRC && (phi.at(b) != 0.0 || psi.at(b) != 0.0))
+            return fail(CTP_EINVAL, "phi and psi must be zero for circular and 2D scans");
+        if (!(sad.at(b) > 0) || !(sdd.at(b) > 0))
+            return fail(CTP_EINVAL, "SAD and SDD must be positive");
+        if (g.det == CTP_DET_CURVED && xsrc.at(b) != 0.0)
+            return fail(CTP_EUNSUPPORTED, "curved detector with a lateral source offset");
+        const Mat3 R = pose(theta.at(b), ph, ps);
+        const Vec3 obj{xo.at(b), yo.at(b), two_d ? 0.0 : zo.at(b)};
+        Frame f;
+        f.s = R * Vec3{xsrc.at(b), sad.at(b), two_d ? 0.0 : zsrc.at(b)} - obj;
+        f.d = R * Vec3{0.0, sad.at(b) - sdd.at(b), 0.0} - obj;
+        f.eu = R * Vec3{1, 0, 0};
+        f.ev = R * Vec3{0, 0, 1};
+        f.n = R * Vec3{0, 1, 0};
+        f.sdd = sdd.at(b);
+        f.ue0 = -0.5 * g.nu * g.du - uo.at(b);
+        f.ve0 = two_d ? -0.5 * g.dv : -0.5 * nv * g.dv - vo.at(b);
+
+        // every corner of the volume box must lie strictly in front of the source
+        double Wmin = 1e300, amax = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            const Vec3 p{(c & 1) ? hx : -hx, (c & 2) ? hy : -hy, (c & 4) ? hz : -hz};
+            const double W = dot(f.s - p, f.n);
+            Wmin = std::fmin(Wmin, W);
+            amax = std::fmax(amax, std::fabs(dot(p - f.s, f.eu)));
+        }
+        const double D = dot(f.s - f.d, f.n);
+        if (!(Wmin > 1e-6 * f.sdd))
+            return fail(CTP_EINVAL, "part of the volume is at or behind the source in view " + std::to_string(b));
+
+        // bound on the transaxial footprint width (columns): |grad u| * voxel extent
+        const double grad = g.det == CTP_DET_FLAT ? D * (Wmin + amax) / (Wmin * Wmin) / g.du
+                                                  : f.sdd / Wmin / g.du;
+        const double ext = method == CTP_SF ? std::sqrt(g.dx * g.dx + g.dy * g.dy) : std::fmax(g.dx, g.dy);
+        kmax = std::fmax(kmax, grad * ext);
+
+        ctp::ViewRec &r = recs[(size_t)b];
+        std::memset(&r, 0, sizeof(r));
+        const Vec3 dms = f.d - f.s;
+        const double vals_eu[3] = {f.eu.x, f.eu.y, f.eu.z}, vals_ev[3] = {f.ev.x, f.ev.y, f.ev.z};
+        const double vals_n[3] = {f.n.x, f.n.y, f.n.z}, vals_s[3] = {f.s.x, f.s.y, f.s.z};
+        const double vals_d[3] = {dms.x, dms.y, dms.z};
+        for (int k = 0; k < 3; ++k) {
+            r.eu[k] = (float)vals_eu[k];
+            r.ev[k] = (float)vals_ev[k];
+            r.n[k] = (float)vals_n[k];
+            r.s[k] = (float)vals_s[k];
+            r.dms[k] = (float)vals_d[k];
+        }
+        r.seu = (float)dot(f.s, f.eu);
+        r.sev = (float)dot(f.s, f.ev);
+        r.sn = (float)dot(f.s, f.n);
+        const Vec3 smd = f.s - f.d;
+        if (g.det == CTP_DET_FLAT) {
+            r.Du = (float)(D / g.du);
+            r.Dv = (float)(D / g.dv);
+            r.cu = (float)((dot(smd, f.eu) - f.ue0) / g.du);
+        } else {
+            r.Du = (float)(f.sdd / g.du);
+            r.Dv = (float)(f.sdd / g.dv);
+            r.cu = (float)(-f.ue0 / g.du);
+        }
+        r.cv = (float)((dot(smd, f.ev) - f.ve0) / g.dv);
+        r.ue0 = (float)f.ue0;
+        r.ve0 = (float)f.ve0;
+        r.sdd = (float)f.sdd;
+        r.sd_ev = (float)dot(smd, f.ev);
+        // distance driven: planes y = const when the detector normal is closer to y
+        r.ydrv = std::fabs(f.n.y) >= std::fabs(f.n.x) ? 1 : 0;
+        r.ddC = (float)(-(dms.z + f.ve0) / g.dv);
+        if (method == CTP_DD) {
+            // every column-edge ray must cross the driving planes
+            for (int i = 0; i <= g.nu; i += (g.nu > 1 ? g.nu : 1)) {
+                const double u = f.ue0 + i * g.du;
+                Vec3 q;
+                if (g.det == CTP_DET_FLAT)
+                    q = dms + u * f.eu;
+                else
+                    q = f.sdd * std::sin(u / f.sdd) * f.eu - f.sdd * std::cos(u / f.sdd) * f.n;
+                const double qa = r.ydrv ? q.y : q.x;
+                const double na = r.ydrv ? -f.n.y : -f.n.x;   // central ray direction component
+                if (!(qa * na > 1e-3 * std::fabs(na) * std::sqrt(q.x * q.x + q.y * q.y)))
+                    return fail(CTP_EINVAL, "detector ray parallel to the driving planes in view " + std::to_string(b));
+            }
+        }
+    }
+    const int need = (int)std::floor(kmax * 1.001 + 1e-6) + 2;
+    if (need > ctp::kMaxCells)
+        return fail(CTP_EUNSUPPORTED, "footprint wider than 16 detector columns");
+
+    ctp_plan *plan = new (std::nothrow) ctp_plan;
+    if (!plan)
+        return fail(CTP_ENOMEM, "host allocation failed");
+    std::memset(plan, 0, sizeof(*plan));
+    plan->g = g;
+    plan->method = method;
+    hipError_t e = hipGetDevice(&plan->device);
+    if (e != hipSuccess) {
+        delete plan;
+        return fail(CTP_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    e = hipMalloc(&plan->d_views, recs.size() * sizeof(ctp::ViewRec));
+    if (e != hipSuccess) {
+        delete plan;
+        return fail(e == hipErrorOutOfMemory ? CTP_ENOMEM : CTP_EDEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(plan->d_views, recs.data(), recs.size() * sizeof(ctp::ViewRec), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(plan->d_views);
+        delete plan;
+        return fail(CTP_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+
+    ctp::LaunchCfg &c = plan->cfg;
+    c.geom = g.kind;
+    c.det = g.det;
+    c.method = method;
+    c.kcells = need <= 3 ? 3 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+    c.n_strips = (g.nu + ctp::kStripW - 1) / ctp::kStripW;
+    c.n_row_chunks = (nv + ctp::kRowsMax - 1) / ctp::kRowsMax;
+
+    ctp::Params &p = plan->base;
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.nz = nz;
+    p.dx = (float)g.dx;
+    p.dy = (float)g.dy;
+    p.dz = (float)(two_d ? 1.0 : g.dz);
+    p.x0 = (float)(-0.5 * (g.nx - 1) * g.dx);
+    p.y0 = (float)(-0.5 * (g.ny - 1) * g.dy);
+    p.z0 = (float)(two_d ? 0.0 : -0.5 * (nz - 1) * g.dz);
+    p.nu = g.nu;
+    p.nv = nv;
+    p.du = (float)g.du;
+    p.dv = (float)(two_d ? 1.0 : g.dv);
+    p.n_views = g.n_views;
+    p.eps = 1e-6f;
+    plan->g.theta = plan->g.phi = plan->g.psi = plan->g.sad = plan->g.sdd = nullptr;
+    plan->g.x_src = plan->g.z_src = plan->g.x_ofst = plan->g.y_ofst = plan->g.z_ofst = nullptr;
+    plan->g.u_ofst = plan->g.v_ofst = nullptr;
+    *out = plan;
+    return CTP_OK;
+}
+
+ctp_status ctp_plan_destroy(ctp_plan *plan)
+{
+    g_last_error.clear();
+    if (plan == nullptr)
+        return CTP_OK;
+    hipError_t e = hipFree(plan->d_views);
+    delete plan;
+    if (e != hipSuccess)
+        return fail(CTP_EDEVICE, std::string("hipFree: ") + hipGetErrorString(e));
+    return CTP_OK;
+}
+
+ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch, size_t *vol_bytes,
+                          size_t *sino_bytes)
+{
+    g_last_error.clear();
+    if (plan == nullptr || batch < 1)
+        return fail(CTP_EINVAL, "NULL plan or batch < 1");
+    if (dtype != CTP_F32)
+        return fail(CTP_EUNSUPPORTED, "only FP32 storage is implemented");
+    const ctp_geometry_desc &g = plan->g;
+    const bool two_d = g.kind == CTP_FAN2D;
+    const size_t nvox = (size_t)g.nx * g.ny * (two_d ? 1 : g.nz);
+    const size_t ncell = (size_t)g.n_views * g.nu * (two_d ? 1 : g.nv);
+    if (vol_bytes)
+        *vol_bytes = nvox * (size_t)batch * sizeof(float);
+    if (sino_bytes)
+        *sino_bytes = ncell * (size_t)batch * sizeof(float);
+    return CTP_OK;
+}
+
+ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t batch, size_t *bytes)
+{
+    size_t vb = 0, sb = 0;
+    ctp_status st = ctp_plan_bytes(plan, CTP_F32, batch, &vb, &sb);
+    if (st != CTP_OK)
+        return st;
+    if (bytes == nullptr)
+        return fail(CTP_EINVAL, "NULL output");
+    if (dir == CTP_FORWARD)
+        *bytes = vb;
+    else if (dir == CTP_BACKWARD)
+        *bytes = (plan->g.kind == CTP_FAN2D && plan->method == CTP_SF) ? 0 : sb;
+    else
+        return fail(CTP_EINVAL, "unknown direction");
+    return CTP_OK;
+}
+
+namespace {
+
+ctp_status prepare_call(const ctp_plan *plan, const void *a, const void *b, ctp_dtype da, ctp_dtype db,
+                        int64_t batch, void *ws, size_t ws_bytes, ctp_direction dir, ctp::Params &p)
+{
+    if (plan == nullptr || a == nullptr || b == nullptr)
+        return fail(CTP_EINVAL, "NULL plan or data pointer");
+    if (batch < 1)
+        return fail(CTP_EINVAL, "batch must be >= 1");
+    if (da != CTP_F32 || db != CTP_F32)
+        return fail(CTP_EUNSUPPORTED, "only FP32 storage is implemented");
+    const bool two_d = plan->g.kind == CTP_FAN2D;
+    if (two_d && batch > (int64_t)1 << 24)
+        return fail(CTP_EINVAL, "2D batch too large");
+    if (!two_d && batch > 65535)
+        return fail(CTP_EINVAL, "batch too large");
+    size_t need = 0;
+    ctp_status st = ctp_workspace_bytes(plan, dir, batch, &need);
+    if (st != CTP_OK)
+        return st;
+    if (need > 0 && (ws == nullptr || ws_bytes < need))
+        return fail(CTP_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (need > 0 && ((uintptr_t)ws & 255u) != 0)
+        return fail(CTP_EINVAL, "workspace must be 256-byte aligned");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+        return fail(CTP_EINVAL, "plan was created on another device");
+    p = plan->base;
+    const ctp_geometry_desc &g = plan->g;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    if (two_d) {
+        // the batch runs along the axial dimension: one "slice" / "row" per item
+        p.nz = (int)batch;
+        p.nv = (int)batch;
+        p.vol_z_stride = plane;
+        p.vol_b_stride = 0;
+        p.sino_row_stride = (int64_t)g.n_views * g.nu;
+        p.sino_view_stride = g.nu;
+        p.sino_b_stride = 0;
+    } else {
+        p.vol_z_stride = plane;
+        p.vol_b_stride = plane * g.nz;
+        p.sino_row_stride = g.nu;
+        p.sino_view_stride = (int64_t)g.nv * g.nu;
+        p.sino_b_stride = (int64_t)g.n_views * g.nv * g.nu;
+    }
+    return CTP_OK;
+}
+
+ctp_status finish(hipError_t e, hipStream_t stream, const char *what)
+{
+    if (e == hipSuccess && sync_debug())
+        e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        return fail(CTP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return CTP_OK;
+}
+
+}  // namespace
+
+ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
+                       ctp_dtype sino_dtype, int64_t batch, int accumulate, void *workspace,
+                       size_t workspace_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    ctp::Params p;
+    ctp_status st = prepare_call(plan, vol, sino, vol_dtype, sino_dtype, batch, workspace,
+                                 workspace_bytes, CTP_FORWARD, p);
+    if (st != CTP_OK)
+        return st;
+    const bool two_d = plan->g.kind == CTP_FAN2D;
+    const int64_t plane = (int64_t)plan->g.nx * plan->g.ny;
+    float *volT = static_cast<float *>(workspace);
+    hipError_t e = two_d ? ctp::launch_transpose_zfast((const float *)vol, volT, 1, batch, plane, stream)
+                         : ctp::launch_transpose_zfast((const float *)vol, volT, batch, plan->g.nz, plane, stream);
+    if (e == hipSuccess)
+        e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, (float *)sino, batch, accumulate, stream);
+    return finish(e, stream, "forward projection");
+}
+
+ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *vol,
+                           ctp_dtype vol_dtype, int64_t batch, int accumulate, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    ctp::Params p;
+    ctp_status st = prepare_call(plan, sino, vol, sino_dtype, vol_dtype, batch, workspace,
+                                 workspace_bytes, CTP_BACKWARD, p);
+    if (st != CTP_OK)
+        return st;
+    const float *ys = (const float *)sino;
+    hipError_t e = hipSuccess;
+    if (!(plan->g.kind == CTP_FAN2D && plan->method == CTP_SF)) {
+        e = ctp::launch_amp_scale(p, plan->cfg, plan->d_views, ys, (float *)workspace, batch, stream);
+        ys = (const float *)workspace;
+    }
+    if (e == hipSuccess)
+        e = ctp::launch_backward(p, plan->cfg, plan->d_views, ys, (float *)vol, batch, accumulate, stream);
+    return finish(e, stream, "back projection");
+}
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: max |gpu - oracle| / max |oracle| <= 1e-4 for FP32 results (forward on the sinogram,
+adjoint on the volume).  Small cases are compared element by element; the benchmark scans
+are compared on sampled views (forward) and sampled voxels (adjoint) that the oracle computes
+one by one, in the same launch configuration the benchmark uses.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2503_16741_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="session")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2503_16741_amd import ctproj
+    ctproj.lib()
+    return torch
+
+
+def rel_err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+def small_geom(kind, det, seed=0, n_views=7, vector=True):
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0, 2 * math.pi, n_views)
+    th[0] = 0.0
+    if n_views > 2:
+        th[1] = math.pi / 4            # exact 45 deg: DD driving-axis tie
+        th[2] = math.pi / 2
+    kw = dict(theta=th, sad=150.0, sdd=260.0, x_ofst=0.6, y_ofst=-0.9, u_ofst=0.37)
+    if kind == "fan2d":
+        g = dict(kind=kind, det=det, nx=45, ny=38, nz=1, dx=0.9, dy=1.0, dz=1.0, nu=101, nv=1,
+                 du=1.1, dv=1.0, n_views=n_views)
+    else:
+        g = dict(kind=kind, det=det, nx=37, ny=29, nz=21, dx=0.8, dy=0.7, dz=0.9, nu=83, nv=45,
+                 du=0.9, dv=1.0, n_views=n_views)
+        kw.update(z_ofst=0.4, v_ofst=-0.6, z_src=1.3)
+    if det == "flat":
+        kw["x_src"] = rng.uniform(-2, 2, n_views) if vector else 0.8
+    if kind == "cone_noncirc":
+        kw.update(phi=rng.uniform(-0.04, 0.04, n_views), psi=rng.uniform(-0.04, 0.04, n_views),
+                  z_src=rng.uniform(-2, 2, n_views))
+    return synth.Geometry(**g, **kw)
+
+
+CASES = [("fan2d", "flat", "sf"), ("fan2d", "curved", "sf"), ("fan2d", "flat", "dd"),
+         ("fan2d", "curved", "dd"), ("cone", "flat", "sf"), ("cone", "curved", "sf"),
+         ("cone", "flat", "dd"), ("cone", "curved", "dd"), ("cone_noncirc", "flat", "sf")]
+
+
+def run_fwd(torch, plan, vol, accumulate_into=None):
+    from paper_2503_16741_amd import ctproj
+    v = torch.from_numpy(np.ascontiguousarray(vol, dtype=np.float32)).cuda()
+    g = plan.geom
+    lead = tuple(v.shape[:v.dim() - len(g.vol_shape)])
+    if accumulate_into is None:
+        s = torch.full(lead + tuple(g.sino_shape), float("nan"), dtype=torch.float32, device="cuda")
+        ctproj.ctp_project(plan, v, s)
+    else:
+        s = torch.from_numpy(np.ascontiguousarray(accumulate_into, dtype=np.float32)).cuda()
+        ctproj.ctp_project(plan, v, s, accumulate=True)
+    torch.cuda.synchronize()
+    return s.cpu().numpy()
+
+
+def run_bwd(torch, plan, sino, accumulate_into=None):
+    from paper_2503_16741_amd import ctproj
+    s = torch.from_numpy(np.ascontiguousarray(sino, dtype=np.float32)).cuda()
+    g = plan.geom
+    lead = tuple(s.shape[:s.dim() - len(g.sino_shape)])
+    if accumulate_into is None:
+        v = torch.full(lead + tuple(g.vol_shape), float("nan"), dtype=torch.float32, device="cuda")
+        ctproj.ctp_backproject(plan, s, v)
+    else:
+        v = torch.from_numpy(np.ascontiguousarray(accumulate_into, dtype=np.float32)).cuda()
+        ctproj.ctp_backproject(plan, s, v, accumulate=True)
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+# ---- small cases, element by element ------------------------------------------------------
+
+@pytest.mark.parametrize("kind,det,method", CASES)
+def test_small_parity(torch_gpu, orc, kind, det, method):
+    from paper_2503_16741_amd import ctproj
+    g = small_geom(kind, det)
+    print(f"case {kind}/{det}/{method}", flush=True)
+    plan = ctproj.ctp_plan_create(g, method)
+    x = synth.random_volume(g, seed=1)
+    y = synth.random_sinogram(g, seed=2)
+    yf = run_fwd(torch_gpu, plan, x)
+    assert np.all(np.isfinite(yf))
+    assert rel_err(yf, orc.forward(g, x, method=method)) <= TOL
+    xb = run_bwd(torch_gpu, plan, y)
+    assert np.all(np.isfinite(xb))
+    assert rel_err(xb, orc.adjoint(g, y, method=method)) <= TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("kind,det,method", CASES)
+def test_gpu_dot_product(torch_gpu, kind, det, method):
+    """<A x, y> = <x, A^T y> for the GPU pair (Eq. 2; FP32 sums, FP64 inner products)."""
+    from paper_2503_16741_amd import ctproj
+    g = small_geom(kind, det, seed=3)
+    plan = ctproj.ctp_plan_create(g, method)
+    x = synth.random_volume(g, seed=4)
+    y = synth.random_sinogram(g, seed=5)
+    lhs = np.sum(run_fwd(torch_gpu, plan, x).astype(np.float64) * y)
+    rhs = np.sum(x.astype(np.float64) * run_bwd(torch_gpu, plan, y))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_scalar_vector_batch_accumulate(torch_gpu, orc):
+    """Scalar and per-view vector parameters agree; batch items are independent; accumulate
+    adds to the output."""
+    from paper_2503_16741_amd import ctproj
+    g1 = small_geom("cone", "flat", seed=6, vector=False)
+    g2 = small_geom("cone", "flat", seed=6, vector=False)
+    g2.x_src = np.full(g2.n_views, g2.x_src)
+    g2.sad = np.full(g2.n_views, 150.0)
+    p1, p2 = ctproj.ctp_plan_create(g1, "sf"), ctproj.ctp_plan_create(g2, "sf")
+    x = synth.random_volume(g1, seed=7, batch=3)
+    a = run_fwd(torch_gpu, p1, x)
+    b = run_fwd(torch_gpu, p2, x)
+    assert np.array_equal(a, b)
+    single = run_fwd(torch_gpu, p1, x[1])
+    assert rel_err(a[1], single) <= 1e-6
+    base = synth.random_sinogram(g1, seed=8, batch=3)
+    acc = run_fwd(torch_gpu, p1, x, accumulate_into=base)
+    assert rel_err(acc, a + base) <= 1e-6
+    y = synth.random_sinogram(g1, seed=9, batch=3)
+    xb = run_bwd(torch_gpu, p1, y)
+    assert rel_err(xb[2], orc.adjoint(g1, y[2])) <= TOL
+    acc_v = run_bwd(torch_gpu, p1, y, accumulate_into=x)
+    assert rel_err(acc_v, xb + x) <= 1e-6
+
+
+def test_2d_large_batch_row_chunks(torch_gpu, orc):
+    """A 2D batch larger than one LDS row chunk (512 items) is split across work-groups."""
+    from paper_2503_16741_amd import ctproj
+    g = synth.Geometry(kind="fan2d", det="flat", nx=24, ny=20, nz=1, dx=1.0, dy=1.0, dz=1.0,
+                       nu=40, nv=1, du=1.5, dv=1.0, n_views=5, theta=synth.full_circle(5),
+                       sad=200.0, sdd=400.0)
+    plan = ctproj.ctp_plan_create(g, "sf")
+    x = synth.random_volume(g, seed=10, batch=600)
+    y = run_fwd(torch_gpu, plan, x)
+    for b in (0, 511, 512, 599):
+        assert rel_err(y[b], orc.forward(g, x[b])) <= TOL
+    s = synth.random_sinogram(g, seed=11, batch=600)
+    xb = run_bwd(torch_gpu, plan, s)
+    for b in (0, 513, 599):
+        assert rel_err(xb[b], orc.adjoint(g, s[b])) <= TOL
+
+
+def test_3d_many_rows(torch_gpu, orc):
+    """More detector rows than one LDS row chunk."""
+    from paper_2503_16741_amd import ctproj
+    g = synth.Geometry(kind="cone", det="flat", nx=12, ny=12, nz=40, dx=1.0, dy=1.0, dz=1.0,
+                       nu=24, nv=700, du=1.2, dv=0.1, n_views=3, theta=np.array([0.1, 1.0, 2.0]),
+                       sad=100.0, sdd=200.0)
+    plan = ctproj.ctp_plan_create(g, "sf")
+    x = synth.random_volume(g, seed=12)
+    assert rel_err(run_fwd(torch_gpu, plan, x), orc.forward(g, x)) <= TOL
+    y = synth.random_sinogram(g, seed=13)
+    assert rel_err(run_bwd(torch_gpu, plan, y), orc.adjoint(g, y)) <= TOL
+
+
+def test_empty_and_determinism(torch_gpu):
+    from paper_2503_16741_amd import ctproj
+    g = small_geom("cone", "flat", seed=14)
+    plan = ctproj.ctp_plan_create(g, "sf")
+    assert not np.any(run_fwd(torch_gpu, plan, np.zeros(g.vol_shape, np.float32)))
+    y = synth.random_sinogram(g, seed=15)
+    a, b = run_bwd(torch_gpu, plan, y), run_bwd(torch_gpu, plan, y)
+    assert np.array_equal(a, b)                  # gather: bitwise repeatable
+    x = synth.random_volume(g, seed=16)
+    f1, f2 = run_fwd(torch_gpu, plan, x), run_fwd(torch_gpu, plan, x)
+    assert rel_err(f1, f2) <= 1e-6               # LDS atomics may reorder FP32 sums
+
+
+def test_errors_are_reported(torch_gpu):
+    import torch
+    from paper_2503_16741_amd import ctproj
+    g = small_geom("cone", "flat", seed=17)
+    plan = ctproj.ctp_plan_create(g, "sf")
+    v = torch.zeros(g.vol_shape, dtype=torch.float32, device="cuda")
+    s = torch.zeros(g.sino_shape, dtype=torch.float32, device="cuda")
+    tiny = torch.zeros(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(ctproj.CtpError) as e:
+        ctproj.ctp_project(plan, v, s, workspace=tiny)
+    assert e.value.status == ctproj.CTP_EINVAL
+    bad = synth.Geometry(**{**small_geom("cone", "flat").__dict__, "sad": 5.0, "sdd": 10.0})
+    with pytest.raises(ctproj.CtpError) as e:
+        ctproj.ctp_plan_create(bad, "sf")
+    assert e.value.status == ctproj.CTP_EINVAL
+
+
+# ---- the benchmark scans, sampled ----------------------------------------------------------
+
+_CACHE = {}
+
+
+def bench_input(name):
+    if name not in _CACHE:
+        g = {"c1": synth.fan2d_c1, "c2": synth.cone_c2, "c3": synth.curved_c3,
+             "c4": synth.noncirc_c4}[name]()
+        _CACHE[name] = (g, synth.phantom(g, seed=0))
+    return _CACHE[name]
+
+
+@pytest.mark.parametrize("name,method,views", [
+    ("c1", "sf", None), ("c1", "dd", None),
+    ("c2", "sf", [0, 45, 137, 359]), ("c2", "dd", [0, 45, 137, 359]),
+    ("c3", "sf", [0, 301]), ("c3", "dd", [90, 500]),
+    ("c4", "sf", [0, 257]),
+])
+def test_benchmark_scan_parity(torch_gpu, orc, name, method, views):
+    from paper_2503_16741_amd import ctproj
+    g, vol = bench_input(name)
+    print(f"scan {name} {method}", flush=True)
+    plan = ctproj.ctp_plan_create(g, method)
+    y = run_fwd(torch_gpu, plan, vol)
+    assert np.all(np.isfinite(y))
+    sel = np.arange(g.n_views) if views is None else np.asarray(views)
+    ref = orc.forward(g, vol, method=method, views=sel)
+    assert rel_err(y[sel], ref) <= TOL
+    # adjoint of a seeded sinogram, sampled voxels
+    ys = synth.random_sinogram(g, seed=1)
+    xb = run_bwd(torch_gpu, plan, ys)
+    assert np.all(np.isfinite(xb))
+    rng = np.random.default_rng(0)
+    idx = rng.choice(g.n_vox, size=min(g.n_vox, 300 if name in ("c3", "c4") else 1500),
+                     replace=False)
+    ref_x = orc.adjoint(g, ys, method=method, voxels=idx)
+    assert rel_err(xb.reshape(-1)[idx], ref_x) <= TOL
+    plan.close()
