@@ -103,8 +103,10 @@ ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch,
                           size_t *vol_bytes, size_t *sino_bytes);
 
 /* Device workspace (bytes) that ctp_project / ctp_backproject need for `batch` items:
- * forward: one transposed copy of the volume (z fastest); backward: one copy of the
- * sinogram scaled by the per-cell amplitude.  May be 0 (2D SF backward needs none). */
+ * forward: 256 bytes for the accumulator scale, one float per 32x32 tile of the volume for
+ * its max |x|, and one z-fastest copy of the volume; backward: one copy of the sinogram
+ * scaled by the per-cell amplitude (0 for 2D SF, which needs none).  The contents are
+ * scratch: nothing is kept between calls. */
 ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t batch,
                                size_t *bytes);
 
@@ -115,6 +117,8 @@ ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t 
  * of at least ctp_workspace_bytes(plan, CTP_FORWARD, batch) bytes, owned by the caller and
  * not used by any other concurrent call; 256-byte alignment required.  Asynchronous on
  * `stream` (0 = null stream); returns after enqueueing.
+ * The volume must be finite: the projector accumulates in 32-bit fixed point whose scale is
+ * set per call from max |vol| (relative resolution ~1e-9 of the largest possible cell sum).
  * Errors: CTP_EINVAL (NULL pointers, batch < 1, workspace too small or misaligned, plan used
  * on another device), CTP_EUNSUPPORTED (dtype other than CTP_F32), CTP_EDEVICE (launch).
  */

@@ -66,15 +66,19 @@ struct Params {
 struct LaunchCfg {
     int geom, det, method, kcells;
     int n_strips, n_row_chunks;
+    float acc_bound;   // bound on a detector cell's pre-amplitude sum per unit |x|
 };
 
-hipError_t launch_transpose_zfast(const float *vol, float *volT, int64_t batch, int64_t nz,
-                                  int64_t plane, hipStream_t st);
+int64_t transpose_blocks(int64_t batch, int64_t nz, int64_t plane);
+hipError_t launch_transpose_zfast(const float *vol, float *volT, float *blockmax, int64_t batch,
+                                  int64_t nz, int64_t plane, hipStream_t st);
+hipError_t launch_qscale(const float *blockmax, int64_t n, float bound, float *qscale,
+                         hipStream_t st);
 hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *views,
                             const float *sino, float *out, int64_t batch, hipStream_t st);
 hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,
-                          const float *volT, float *sino, int64_t batch, int accumulate,
-                          hipStream_t st);
+                          const float *volT, const float *qscale, float *sino, int64_t batch,
+                          int accumulate, hipStream_t st);
 hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,
                            const float *ysc, float *vol, int64_t batch, int accumulate,
                            hipStream_t st);

@@ -402,10 +402,16 @@ constexpr int kListCap = 2048;
 template <int GEOM, int DET, int METHOD, int K>
 __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
                                                   const float *__restrict__ volT,
+                                                  const float *__restrict__ qscale,
                                                   float *__restrict__ sino, int accumulate,
                                                   int n_row_chunks)
 {
-    extern __shared__ float acc[];           // [R][kStripW + 1]
+    // Fixed-point accumulators: on gfx950 an LDS integer add costs a few cycles per
+    // wavefront while the FP32 LDS atomic is far slower.  Contributions are scaled by
+    // 2^S (qscale[0], chosen per call from max |x| so the strip sums fit in 31 bits) and
+    // rounded to nearest; integer sums are also order independent, so the result is
+    // bitwise repeatable.
+    extern __shared__ int acc[];             // [R][kStripW + 1]
     __shared__ int s_count;
     __shared__ unsigned short s_list[kListCap];
 
@@ -422,7 +428,8 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
     constexpr int SW = kStripW + 1;
 
     for (int e = threadIdx.x; e < R * SW; e += blockDim.x)
-        acc[e] = 0.0f;
+        acc[e] = 0;
+    const float qs = qscale[0], qinv = qscale[1];
 
     const float hz = 0.5f * P.dz;
     const float zb0 = P.z0 - hz - V.s[2];               // bottom face of slice 0, minus z_src
@@ -493,28 +500,28 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                     float sw[K];
 #pragma unroll
                     for (int k = 0; k < K; ++k)
-                        sw[k] = readlane_f(w[k], c);
+                        sw[k] = readlane_f(w[k], c) * qs;
                     const float s_an = readlane_f(an, c), s_bn = readlane_f(bn, c);
                     const float s_af = readlane_f(af, c), s_bf = readlane_f(bf, c);
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
-                    float *accs = acc + s_slot;
+                    int *accs = acc + s_slot;
                     for (int z = zbeg + lane; z < zend; z += 64) {
                         const float val = colp[z];
                         if constexpr (GEOM == kFan2D) {
-                            float *a = accs + (z - r0) * SW;
+                            int *a = accs + (z - r0) * SW;
 #pragma unroll
                             for (int k = 0; k < K; ++k)
                                 if (k < s_nc)
-                                    atomicAdd(a + k, val * sw[k]);
+                                    atomicAdd(a + k, __float2int_rn(val * sw[k]));
                         } else {
                             const Trap tr = sf_axial(s_an, s_bn, s_af, s_bf, (float)z, P.eps);
                             for_rows(tr, R, [&](int j, float F) {
                                 const float f = F * val;
-                                float *a = accs + j * SW;
+                                int *a = accs + j * SW;
 #pragma unroll
                                 for (int k = 0; k < K; ++k)
                                     if (k < s_nc)
-                                        atomicAdd(a + k, f * sw[k]);
+                                        atomicAdd(a + k, __float2int_rn(f * sw[k]));
                             });
                         }
                     }
@@ -548,14 +555,15 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                         cc.amp = s_amp;
                         float w[K];
                         sf_cell_weights<K>(cc, cs, nc, P.eps, w);
-                        float *accs = acc + (cs - i_lo);
+                        int *accs = acc + (cs - i_lo);
+                        const float vq = val * qs;
                         for_rows(vx.ax, R, [&](int j, float F) {
-                            const float f = F * val;
-                            float *a = accs + j * SW;
+                            const float f = F * vq;
+                            int *a = accs + j * SW;
 #pragma unroll
                             for (int k = 0; k < K; ++k)
                                 if (k < nc)
-                                    atomicAdd(a + k, f * w[k]);
+                                    atomicAdd(a + k, __float2int_rn(f * w[k]));
                         });
                     }
                 }
@@ -575,21 +583,21 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                     float sfx[K], sal[K], sbe[K];
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        sfx[k] = readlane_f(fx[k], c);
+                        sfx[k] = readlane_f(fx[k], c) * qs;
                         const float bk = readlane_f(bz[k], c);
                         sal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
                         sbe[k] = bk * P.dz;
                     }
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
-                    float *accs = acc + s_slot;
+                    int *accs = acc + s_slot;
                     for (int z = zbeg + lane; z < zend; z += 64) {
                         const float val = colp[z];
                         if constexpr (GEOM == kFan2D) {
-                            float *a = accs + (z - r0) * SW;
+                            int *a = accs + (z - r0) * SW;
 #pragma unroll
                             for (int k = 0; k < K; ++k)
                                 if (k < s_nc)
-                                    atomicAdd(a + k, val * sfx[k]);
+                                    atomicAdd(a + k, __float2int_rn(val * sfx[k]));
                         } else {
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
@@ -599,7 +607,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                                 const float zh = zl + sbe[k];
                                 const float vk = val * sfx[k];
                                 for_dd_rows(zl, zh, R, [&](int j, float wz) {
-                                    atomicAdd(accs + j * SW + k, vk * wz);
+                                    atomicAdd(accs + j * SW + k, __float2int_rn(vk * wz));
                                 });
                             }
                         }
@@ -617,7 +625,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
         if (i >= i_hi)
             continue;
         const int j = r0 + row;
-        const float val = acc[row * SW + k] * cell_amp<GEOM, DET, METHOD>(V, P, i, j);
+        const float val = (float)acc[row * SW + k] * qinv * cell_amp<GEOM, DET, METHOD>(V, P, i, j);
         float *dst = sino + (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
                      (int64_t)j * P.sino_row_stride + i;
         *dst = accumulate ? *dst + val : val;
@@ -808,26 +816,71 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
 // ============================================================================================
 // Helpers: z-fastest copy of the volume, amplitude-scaled copy of the sinogram
 // ============================================================================================
+// z-fastest copy of the volume; also writes max |x| of each block to blockmax.
 __global__ __launch_bounds__(256) void transpose_zfast_kernel(const float *__restrict__ in,
                                                               float *__restrict__ out,
+                                                              float *__restrict__ blockmax,
                                                               int64_t nz, int64_t plane)
 {
     __shared__ float tile[32][33];
+    __shared__ float wmax[4];
     const int64_t b = blockIdx.z;
     const int64_t p0 = (int64_t)blockIdx.x * 32, z0 = (int64_t)blockIdx.y * 32;
     const float *src = in + b * nz * plane;
     float *dst = out + b * nz * plane;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    float m = 0.0f;
     for (int r = ty; r < 32; r += 8) {
         const int64_t z = z0 + r, p = p0 + tx;
-        if (z < nz && p < plane)
-            tile[r][tx] = src[z * plane + p];
+        if (z < nz && p < plane) {
+            const float v = src[z * plane + p];
+            tile[r][tx] = v;
+            m = fmaxf(m, fabsf(v));
+        }
     }
+    for (int off = 32; off > 0; off >>= 1)
+        m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0)
+        wmax[threadIdx.x >> 6] = m;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        blockmax[blk] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    }
     for (int r = ty; r < 32; r += 8) {
         const int64_t p = p0 + r, z = z0 + tx;
         if (z < nz && p < plane)
             dst[p * nz + z] = tile[tx][r];
+    }
+}
+
+// Fixed-point scale of the forward accumulators: 2^S with S the largest integer such that
+// max|x| * bound * 2^S <= 2^30 (bound: largest possible pre-amplitude sum per detector cell
+// per unit density).  qscale = {2^S, 2^-S}.
+__global__ __launch_bounds__(1024) void qscale_kernel(const float *__restrict__ blockmax,
+                                                      int64_t n, float bound,
+                                                      float *__restrict__ qscale)
+{
+    __shared__ float red[16];
+    float m = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        m = fmaxf(m, blockmax[i]);
+    for (int off = 32; off > 0; off >>= 1)
+        m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            m = fmaxf(m, red[w]);
+        int S = 0;
+        const float top = m * bound;
+        if (top > 0.0f && isfinite(top)) {
+            S = (int)floorf(30.0f - log2f(top));
+            S = max(-100, min(S, 100));
+        }
+        qscale[0] = ldexpf(1.0f, S);
+        qscale[1] = ldexpf(1.0f, -S);
     }
 }
 
@@ -852,8 +905,8 @@ __global__ __launch_bounds__(256) void amp_scale_kernel(Params P, const ViewRec 
 
 template <int GEOM, int DET, int METHOD, int K>
 hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
-                      const float *volT, float *sino, int64_t batch, int accumulate,
-                      hipStream_t st)
+                      const float *volT, const float *qscale, float *sino, int64_t batch,
+                      int accumulate, hipStream_t st)
 {
     const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
     const int R = min(kRowsMax, rows_total);
@@ -861,7 +914,7 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
     dim3 grid(c.n_strips, p.n_views, (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks));
     hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(256), lds, st, p, views,
-                       volT, sino, accumulate, nchunks);
+                       volT, qscale, sino, accumulate, nchunks);
     return hipGetLastError();
 }
 
@@ -921,10 +974,10 @@ hipError_t dispatch(const LaunchCfg &c, A &&...a)
 template <int G, int D, int M, int K>
 struct FwdOp {
     static hipError_t run(const Params &p, const LaunchCfg &c, const ViewRec *views,
-                          const float *volT, float *sino, int64_t batch, int accumulate,
-                          hipStream_t st)
+                          const float *volT, const float *qscale, float *sino, int64_t batch,
+                          int accumulate, hipStream_t st)
     {
-        return fwd_launch<G, D, M, K>(p, c, views, volT, sino, batch, accumulate, st);
+        return fwd_launch<G, D, M, K>(p, c, views, volT, qscale, sino, batch, accumulate, st);
     }
 };
 
@@ -949,11 +1002,24 @@ struct AmpOp {
 
 }  // namespace
 
-hipError_t launch_transpose_zfast(const float *vol, float *volT, int64_t batch, int64_t nz,
-                                  int64_t plane, hipStream_t st)
+int64_t transpose_blocks(int64_t batch, int64_t nz, int64_t plane)
+{
+    return ((plane + 31) / 32) * ((nz + 31) / 32) * batch;
+}
+
+hipError_t launch_transpose_zfast(const float *vol, float *volT, float *blockmax, int64_t batch,
+                                  int64_t nz, int64_t plane, hipStream_t st)
 {
     dim3 grid((unsigned)((plane + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)batch);
-    hipLaunchKernelGGL(transpose_zfast_kernel, grid, dim3(256), 0, st, vol, volT, nz, plane);
+    hipLaunchKernelGGL(transpose_zfast_kernel, grid, dim3(256), 0, st, vol, volT, blockmax, nz,
+                       plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_qscale(const float *blockmax, int64_t n, float bound, float *qscale,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(qscale_kernel, dim3(1), dim3(1024), 0, st, blockmax, n, bound, qscale);
     return hipGetLastError();
 }
 
@@ -966,10 +1032,10 @@ hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *
 }
 
 hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,
-                          const float *volT, float *sino, int64_t batch, int accumulate,
-                          hipStream_t st)
+                          const float *volT, const float *qscale, float *sino, int64_t batch,
+                          int accumulate, hipStream_t st)
 {
-    return dispatch<FwdOp>(c, p, c, views, volT, sino, batch, accumulate, st);
+    return dispatch<FwdOp>(c, p, c, views, volT, qscale, sino, batch, accumulate, st);
 }
 
 hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,

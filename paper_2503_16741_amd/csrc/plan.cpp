@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -301,6 +302,15 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     c.kcells = need <= 3 ? 3 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
     c.n_strips = (g.nu + ctp::kStripW - 1) / ctp::kStripW;
     c.n_row_chunks = (nv + ctp::kRowsMax - 1) / ctp::kRowsMax;
+    // Largest possible pre-amplitude sum of one detector cell per unit |x|: SF sums
+    // footprint x amplitude, at most a few times the path through the volume box; DD sums
+    // overlap fractions, at most one per driving plane.  Generous factors keep the forward
+    // projector's fixed-point accumulators far from overflow.
+    {
+        const double lx = g.nx * g.dx, ly = g.ny * g.dy, lz = two_d ? 0.0 : nz * g.dz;
+        c.acc_bound = method == CTP_SF ? (float)(4.0 * std::sqrt(lx * lx + ly * ly + lz * lz))
+                                       : (float)(2.0 * (std::max(g.nx, g.ny) + 2));
+    }
 
     ctp::Params &p = plan->base;
     p.nx = g.nx;
@@ -356,6 +366,34 @@ ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch, 
     return CTP_OK;
 }
 
+namespace {
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Forward workspace: [0, 256) fixed-point scale, then the per-block max|x| of the transpose,
+// then the z-fastest copy of the volume.
+struct FwdWs {
+    size_t blockmax_off, volT_off, total;
+    int64_t nblocks, tr_batch, tr_nz, plane;
+};
+
+FwdWs fwd_ws_layout(const ctp_plan *plan, int64_t batch)
+{
+    const ctp_geometry_desc &g = plan->g;
+    const bool two_d = g.kind == CTP_FAN2D;
+    FwdWs w;
+    w.plane = (int64_t)g.nx * g.ny;
+    w.tr_batch = two_d ? 1 : batch;
+    w.tr_nz = two_d ? batch : g.nz;
+    w.nblocks = ctp::transpose_blocks(w.tr_batch, w.tr_nz, w.plane);
+    w.blockmax_off = 256;
+    w.volT_off = w.blockmax_off + align256((size_t)w.nblocks * sizeof(float));
+    w.total = w.volT_off + (size_t)w.tr_batch * w.tr_nz * w.plane * sizeof(float);
+    return w;
+}
+
+}  // namespace
+
 ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t batch, size_t *bytes)
 {
     size_t vb = 0, sb = 0;
@@ -365,7 +403,7 @@ ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t 
     if (bytes == nullptr)
         return fail(CTP_EINVAL, "NULL output");
     if (dir == CTP_FORWARD)
-        *bytes = vb;
+        *bytes = fwd_ws_layout(plan, batch).total;
     else if (dir == CTP_BACKWARD)
         *bytes = (plan->g.kind == CTP_FAN2D && plan->method == CTP_SF) ? 0 : sb;
     else
@@ -443,13 +481,18 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
                                  workspace_bytes, CTP_FORWARD, p);
     if (st != CTP_OK)
         return st;
-    const bool two_d = plan->g.kind == CTP_FAN2D;
-    const int64_t plane = (int64_t)plan->g.nx * plan->g.ny;
-    float *volT = static_cast<float *>(workspace);
-    hipError_t e = two_d ? ctp::launch_transpose_zfast((const float *)vol, volT, 1, batch, plane, stream)
-                         : ctp::launch_transpose_zfast((const float *)vol, volT, batch, plan->g.nz, plane, stream);
+    const FwdWs w = fwd_ws_layout(plan, batch);
+    char *ws = static_cast<char *>(workspace);
+    float *qscale = reinterpret_cast<float *>(ws);
+    float *blockmax = reinterpret_cast<float *>(ws + w.blockmax_off);
+    float *volT = reinterpret_cast<float *>(ws + w.volT_off);
+    hipError_t e = ctp::launch_transpose_zfast((const float *)vol, volT, blockmax, w.tr_batch, w.tr_nz,
+                                               w.plane, stream);
     if (e == hipSuccess)
-        e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, (float *)sino, batch, accumulate, stream);
+        e = ctp::launch_qscale(blockmax, w.nblocks, plan->cfg.acc_bound, qscale, stream);
+    if (e == hipSuccess)
+        e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, qscale, (float *)sino, batch,
+                                accumulate, stream);
     return finish(e, stream, "forward projection");
 }
 
