@@ -63,7 +63,60 @@ def load_traffic(kernel_name):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(geom, vol, n_views=32, n_vox=200000):
+KERNEL_KEYS = {"fwd_kernel": "sf_forward", "bwd_kernel": "sf_backward",
+               "transpose_zfast_kernel": "transpose", "amp_scale_kernel": "amp_scale"}
+
+
+def summarize_traffic(fetch_csv, write_csv):
+    """Turn two rocprofv3 --pmc runs of `bench.py --traffic-probe` (FETCH_SIZE, WRITE_SIZE; KiB
+    per dispatch) into HBM bytes per launch, calibrated by the 512 MiB device copy in the same
+    run (bytes read and written by that copy are known).  Writes profiles/traffic.json and
+    profiles/traffic_sf_c2.md."""
+    import csv
+    import collections
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(float)
+        names = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            names[r["Dispatch_Id"]] = r["Kernel_Name"]
+        return [(names[d], acc[d]) for d in sorted(acc, key=int)]
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = 128 << 22
+    f_copy = [v for n, v in fetch if "copyBuffer" in n][0] * 1024
+    w_copy = [v for n, v in write if "copyBuffer" in n][0] * 1024
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    out = {"source_hash": kernel_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernels": {}}
+    lines = ["# HBM traffic per launch, SF 256^3 x 360 views (rocprofv3 PMC)", "",
+             "Commands (repository root, one MI355X):", "", "```",
+             "rocprofv3 --kernel-trace --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o t --output-format csv -- python3 bench.py --traffic-probe",
+             "rocprofv3 --kernel-trace --pmc WRITE_SIZE -d gpurun_out/pmc_write -o t --output-format csv -- python3 bench.py --traffic-probe",
+             "python3 bench.py --summarize-traffic gpurun_out/pmc_fetch/t_counter_collection.csv gpurun_out/pmc_write/t_counter_collection.csv",
+             "```", "",
+             f"Calibration: a 512 MiB device copy in the same process reads FETCH_SIZE x {f_scale:.4f} and "
+             f"writes WRITE_SIZE x {w_scale:.4f} of its known bytes; those factors scale every kernel below.",
+             f"Kernel source hash: `{out['source_hash']}`.", "",
+             "| kernel | read MB | written MB | total MB |", "|---|---|---|---|"]
+    for (nf, vf), (nw, vw) in zip(fetch, write):
+        key = next((v for k, v in KERNEL_KEYS.items() if k in nf), None)
+        if key is None:
+            continue
+        rd, wr = vf * 1024 * f_scale, vw * 1024 * w_scale
+        out["kernels"][key] = {"read_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr}
+        lines.append(f"| {key} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {(rd + wr) / 1e6:.1f} |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    with open(os.path.join(ROOT, "profiles", "traffic_sf_c2.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def cpu_baseline(geom, vol, n_views=128, n_vox=1500000):
     """Time the FP64 oracle on a bounded sample of the same scan."""
     import numpy as np
     import oracle
@@ -94,7 +147,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dd", action="store_true")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run a 512 MiB device copy, one SF forward and one SF back projection "
+                         "(for FETCH_SIZE / WRITE_SIZE counter runs) and exit")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(views would shard with no exchange; the adjoint needs one all-reduce)",
@@ -139,6 +199,17 @@ def main():
         return wall, fwd, bwd, pair
 
     plan = ctproj.ctp_plan_create(g, "sf")
+    if args.traffic_probe:
+        # a plain copy of known size calibrates the counters; then one call of each kernel
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ctproj.ctp_project(plan, vol, sino)
+        ctproj.ctp_backproject(plan, sino, back)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": src.numel() * 4}), flush=True)
+        return
     wall, fwd, bwd, pair = run(plan, args.steps, args.warmup, "SF")
     vv = float(g.n_vox) * g.n_views
     value = 2.0 * vv * args.steps / wall / 1e9

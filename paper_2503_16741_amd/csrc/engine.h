@@ -16,7 +16,10 @@ enum Method : int { kSF = 0, kDD = 1 };
 constexpr int kStripW = 16;      // detector columns owned by one forward work-group
 constexpr int kMaxCells = 16;    // widest supported transaxial footprint (columns)
 constexpr int kRowsMax = 512;    // detector rows (or 2D batch items) held in LDS at once
-constexpr int kZChunk = 16;      // voxels per lane along z in the back projector
+#ifndef CTP_ZCHUNK
+#define CTP_ZCHUNK 16
+#endif
+constexpr int kZChunk = CTP_ZCHUNK; // voxels per lane along z in the back projector
 constexpr int kTile = 8;         // 8 x 8 voxel columns per wavefront tile
 
 // Per-view constants, object-centred coordinates (the object offset is folded into the

@@ -22,10 +22,32 @@
 
 #include <hip/hip_runtime.h>
 
+#ifndef CTP_FWD_FAST
+#define CTP_FWD_FAST 0
+#endif
+#ifndef CTP_CVT_TRUNC
+#define CTP_CVT_TRUNC 1
+#endif
+
 namespace ctp {
 namespace {
 
+// FP32 -> fixed point for the forward accumulators.  Truncation toward zero (one
+// instruction) biases each term by at most one unit of 2^-S; with the scale set so the
+// largest possible cell sum is 2^30 units, a thousand terms move a cell by ~1e-6 of that.
+__device__ __forceinline__ int to_fixed(float x)
+{
+#if CTP_CVT_TRUNC
+    return (int)x;
+#else
+    return __float2int_rn(x);
+#endif
+}
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// a / b with the hardware reciprocal (1 ulp); used where the quotient feeds a footprint
+// coordinate whose FP32 rounding is already larger.
+__device__ __forceinline__ float fdiv(float a, float b) { return a * fast_rcp(b); }
 
 __device__ __forceinline__ float readlane_f(float v, int lane)
 {
@@ -107,12 +129,12 @@ __device__ __forceinline__ void sf_column(const ViewRec &V, const Params &P, flo
     const float dW[4] = {-wx - wy, wx - wy, -wx + wy, wx + wy};
     float t[4], mn = 3.0e38f, mx = 0.0f, uc;
     if (DET == kFlat) {
-        uc = fmaf(V.Du, ac / Wc, V.cu);
+        uc = fmaf(V.Du, fdiv(ac, Wc), V.cu);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float Wk = Wc + dW[k];
             // u_k - u_c without cancellation: Du (da W_c - a_c dW) / (W_k W_c)
-            t[k] = V.Du * (fmaf(da[k], Wc, -ac * dW[k]) / (Wk * Wc));
+            t[k] = V.Du * fdiv(fmaf(da[k], Wc, -ac * dW[k]), Wk * Wc);
             mn = fminf(mn, Wk);
             mx = fmaxf(mx, Wk);
         }
@@ -136,11 +158,11 @@ __device__ __forceinline__ void sf_column(const ViewRec &V, const Params &P, flo
     c.t2 = t[2] + base;
     c.t3 = t[3] + base;
     sort4(c.t0, c.t1, c.t2, c.t3);
-    c.An = V.Dv / mn;
-    c.Af = V.Dv / mx;
+    c.An = fdiv(V.Dv, mn);
+    c.Af = fdiv(V.Dv, mx);
     const float gx = xc - V.s[0], gy = yc - V.s[1];
     const float g = sqrtf(fmaf(gx, gx, gy * gy));
-    c.amp = g * fminf(P.dx / fabsf(gx), P.dy / fabsf(gy));
+    c.amp = g * fminf(fdiv(P.dx, fabsf(gx)), fdiv(P.dy, fabsf(gy)));
 }
 
 // Cell weights amp * F1 for K consecutive columns starting at absolute column cs.
@@ -165,7 +187,7 @@ __device__ __forceinline__ void sf_cell_weights(const SFCol &c, int cs, int nc, 
 template <int DET>
 __device__ __forceinline__ float dd_detector_u(const ViewRec &V, float a, float W)
 {
-    return DET == kFlat ? fmaf(V.Du, a / W, V.cu) : fmaf(V.Du, atan2f(a, W), V.cu);
+    return DET == kFlat ? fmaf(V.Du, fdiv(a, W), V.cu) : fmaf(V.Du, atan2f(a, W), V.cu);
 }
 
 template <int DET>
@@ -214,17 +236,17 @@ __device__ __forceinline__ void dd_cell_weights(const ViewRec &V, const Params &
     const float dist = plane - sa;
     float qx, qy;
     dd_ray_xy<DET>(V, fmaf((float)cs, P.du, V.ue0), qx, qy);
-    float Xprev = fmaf(dist, (yd ? qx : qy) / (yd ? qy : qx), sb);
+    float Xprev = fmaf(dist, fdiv(yd ? qx : qy, yd ? qy : qx), sb);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         dd_ray_xy<DET>(V, fmaf((float)(cs + k + 1), P.du, V.ue0), qx, qy);
-        const float X = fmaf(dist, (yd ? qx : qy) / (yd ? qy : qx), sb);
+        const float X = fmaf(dist, fdiv(yd ? qx : qy, yd ? qy : qx), sb);
         const float mlo = fminf(X, Xprev), mhi = fmaxf(X, Xprev);
         const float ov = fminf(hi, mhi) - fmaxf(lo, mlo);
-        fx[k] = (k < nc && ov > 0.0f) ? ov / (mhi - mlo) : 0.0f;
+        fx[k] = (k < nc && ov > 0.0f) ? fdiv(ov, mhi - mlo) : 0.0f;
         Xprev = X;
         dd_ray_xy<DET>(V, fmaf((float)cs + (float)k + 0.5f, P.du, V.ue0), qx, qy);
-        bz[k] = (yd ? qy : qx) / (dist * P.dv);
+        bz[k] = fdiv(yd ? qy : qx, dist * P.dv);
     }
 }
 
@@ -364,7 +386,7 @@ __device__ __forceinline__ float sf_amp(const ViewRec &V, const Params &P, float
 {
     const float gx = xc - V.s[0], gy = yc - V.s[1];
     const float g = sqrtf(fmaf(gx, gx, gy * gy));
-    return g * fminf(P.dx / fabsf(gx), P.dy / fabsf(gy));
+    return g * fminf(fdiv(P.dx, fabsf(gx)), fdiv(P.dy, fabsf(gy)));
 }
 
 // ---- tile culling --------------------------------------------------------------------------
@@ -394,13 +416,153 @@ __device__ __forceinline__ void box_u_range(const ViewRec &V, const Params &P, f
     }
 }
 
+
+// ---- forward fast path: axial resampling of one voxel column (circular SF) ----------------
+//
+// For a circular scan the v-projection of the face z = z_f of a voxel column is an interval
+// [p_f, q_f] whose ends are affine in f (nearest / farthest corner).  When consecutive faces'
+// intervals do not overlap, voxel z's SF-TT axial trapezoid rises over face z's interval, is
+// flat up to face z+1 and falls over face z+1's interval, so the column's axial profile
+// sum_z x_z trap_z(v) is piecewise linear and its integral C(t) up to row edge t is
+//   plateau of voxel z:  C(t) = S_z + x_z (w_z / 2 + t - q_z)
+//   inside face z:       C(t) = S_z - x_{z-1} (q_z - t)^2 / (2 w_z) + x_z (t - p_z)^2 / (2 w_z)
+// with S_z = sum_{z' < z} x_z' area_z' and area_z = mid_{z+1} - mid_z (mid: face centre).
+// Row j of the column receives C(j+1) - C(j) -- the same value as summing each voxel's
+// G(j+1) - G(j) -- so every row is touched once per column instead of once per voxel.
+// C is kept in 32-bit fixed point (scale qs) with wrapping arithmetic: the prefix S_z is an
+// exact integer scan, and row values are exact differences.
+// Lanes hold 4 consecutive voxels; each lane writes C at the row edges its voxels own into
+// the wavefront's LDS buffer cbuf[0..R]; then lanes run over rows and add the row value times
+// the column's transaxial weights to the strip.
+__device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float bf, int nz)
+{
+    // faces z and z+1 disjoint for every z: an + bn z <= af + bf (z+1) and vice versa
+    const float zl = (float)(nz - 1);
+    const float m = 1e-4f;
+    return bn > 1e-3f && bf > 1e-3f &&
+           an - af - bf <= -m && fmaf(bn - bf, zl, an - af - bf) <= -m &&
+           af - an - bn <= -m && fmaf(bf - bn, zl, af - an - bn) <= -m;
+}
+
+template <int K>
+__device__ __forceinline__ void sf_column_fast(const float *__restrict__ colp, int nz, float an,
+                                               float bn, float af, float bf, float qs,
+                                               const float (&w)[K], int nc, int *accs, int SW,
+                                               int R, unsigned *cbuf, int lane)
+{
+    const float fR = (float)R;
+    uint32_t carry = 0;       // S at the start of this 256-voxel chunk
+    for (int zb = 0; zb < nz; zb += 256) {
+        const int z0 = zb + 4 * lane;
+        float v[4];
+        if ((nz & 3) == 0 && z0 + 3 < nz) {
+            const float4 v4 = *reinterpret_cast<const float4 *>(colp + z0);
+            v[0] = v4.x; v[1] = v4.y; v[2] = v4.z; v[3] = v4.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
+        }
+        float p[5], qf[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            const float zf = (float)min(z0 + f, nz);
+            const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
+            p[f] = fminf(vn, vf);
+            qf[f] = fmaxf(vn, vf);
+        }
+        uint32_t a[4], T = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float area = 0.5f * ((p[q + 1] + qf[q + 1]) - (p[q] + qf[q]));
+            a[q] = (uint32_t)__float2int_rn(v[q] * qs * area);
+            T += a[q];
+        }
+        // exclusive scan of the lane totals
+        uint32_t incl = T;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)incl, d);
+            if (lane >= d)
+                incl += o;
+        }
+        uint32_t S = carry + incl - T;
+        float vm1 = __shfl_up(v[3], 1);
+        if (lane == 0)
+            vm1 = zb > 0 ? colp[zb - 1] : 0.0f;   // voxel just below the chunk
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (z0 + q < nz) {
+                const int tb = max((int)ceilf(fmaxf(p[q], -1.0f)), 0);
+                const int te = min((int)ceilf(fminf(p[q + 1], fR + 1.0f)), R + 1);
+                const float wq = qf[q] - p[q];
+                for (int t = tb; t < te; ++t) {
+                    const float ft = (float)t;
+                    float local;
+                    if (ft < qf[q] && wq > 1e-12f) {
+                        const float h = 0.5f * fast_rcp(wq);
+                        const float d1 = ft - p[q], d2 = qf[q] - ft;
+                        local = (v[q] * d1 * d1 - vm1 * d2 * d2) * h;
+                    } else {
+                        local = v[q] * (0.5f * wq + (ft - qf[q]));
+                    }
+                    cbuf[t] = S + (uint32_t)__float2int_rn(local * qs);
+                }
+            }
+            S += a[q];
+            vm1 = v[q];
+        }
+        carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    }
+    const float vtop = colp[nz - 1];
+    // edges at and above the top face belong to the space above the column
+    {
+        const float zf = (float)nz;
+        const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
+        const float pt = fminf(vn, vf), qt = fmaxf(vn, vf), wt = qt - pt;
+        const int tb = max((int)ceilf(fmaxf(pt, -1.0f)), 0);
+        const int te = min((int)floorf(fminf(qt, fR)) + 1, R);       // inclusive
+        for (int t = tb + lane; t <= te; t += 64) {
+            const float ft = (float)t;
+            float local = 0.0f;
+            if (ft < qt && wt > 1e-12f) {
+                const float d2 = qt - ft;
+                local = -vtop * d2 * d2 * 0.5f * fast_rcp(wt);
+            }
+            cbuf[t] = carry + (uint32_t)__float2int_rn(local * qs);
+        }
+        // the edge just below the bottom face
+        const float vn0 = an, vf0 = af;
+        const float p0 = fminf(vn0, vf0);
+        const int tl = (int)floorf(fmaxf(p0, -1.0f));
+        if (lane == 0 && tl >= 0 && tl <= R && (float)tl < p0)
+            cbuf[tl] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        // rows of the column inside [0, R)
+        const int jA = max(tl, 0);
+        const int jB = min((int)floorf(fminf(qt, fR)), R - 1);
+        for (int j = jA + lane; j <= jB; j += 64) {
+            const float rv = (float)(int)(cbuf[j + 1] - cbuf[j]);
+            int *a = accs + j * SW;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < nc)
+                    atomicAdd(a + k, __float2int_rn(rv * w[k]));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 constexpr int kListCap = 2048;
 
 // ============================================================================================
 // Forward projector
 // ============================================================================================
+constexpr int kFwdThreads = 512;
+constexpr int kFwdWaves = kFwdThreads / 64;
+
 template <int GEOM, int DET, int METHOD, int K>
-__global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
+__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
                                                   const float *__restrict__ volT,
                                                   const float *__restrict__ qscale,
                                                   float *__restrict__ sino, int accumulate,
@@ -412,13 +574,21 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
     // rounded to nearest; integer sums are also order independent, so the result is
     // bitwise repeatable.
     extern __shared__ int acc[];             // [R][kStripW + 1]
-    __shared__ int s_count;
+    __shared__ int s_count, s_next;
     __shared__ unsigned short s_list[kListCap];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int strip = blockIdx.x, view = blockIdx.y;
-    const int chunk = blockIdx.z % n_row_chunks;
-    const int b = blockIdx.z / n_row_chunks;            // batch item (3D); 0 in 2D
+    // XCD-aware order: work-group i runs on XCD i % 8; each XCD takes the strips
+    // s = xcd, xcd + 8, ... and walks all views of a strip in order, so the work-groups that
+    // share an XCD's L2 project neighbouring views of the same strip (their voxel wedges
+    // overlap) and every XCD gets a mix of central and edge strips.
+    const int n_strips = (P.nu + kStripW - 1) / kStripW;
+    const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
+    if (kk >= ((n_strips - xcd + 7) >> 3) * P.n_views)
+        return;
+    const int strip = xcd + 8 * (kk / P.n_views), view = kk % P.n_views;
+    const int chunk = blockIdx.y % n_row_chunks;
+    const int b = blockIdx.y / n_row_chunks;            // batch item (3D); 0 in 2D
     const int i_lo = strip * kStripW;
     const int i_hi = min(i_lo + kStripW, P.nu);
     const int rows_total = GEOM == kFan2D ? P.nz : P.nv;
@@ -427,6 +597,8 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
     const ViewRec V = views[view];
     constexpr int SW = kStripW + 1;
 
+    // per-wavefront row-edge buffer of the fast path, after the accumulators
+    unsigned *cbuf = reinterpret_cast<unsigned *>(acc + R * SW) + wave * (R + 1);
     for (int e = threadIdx.x; e < R * SW; e += blockDim.x)
         acc[e] = 0;
     const float qs = qscale[0], qinv = qscale[1];
@@ -445,10 +617,12 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
 
     for (int t0 = 0; t0 < ntiles; t0 += kListCap) {
         const int tend = min(t0 + kListCap, ntiles);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             s_count = 0;
+            s_next = 0;
+        }
         __syncthreads();
-        for (int tt = t0 + wave * 64; tt < tend; tt += 256) {
+        for (int tt = t0 + wave * 64; tt < tend; tt += kFwdThreads) {
             const int t = tt + lane;
             bool hit = false;
             if (t < tend) {
@@ -473,7 +647,14 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
         __syncthreads();
         const int nhit = s_count;
 
-        for (int h = wave; h < nhit; h += 4) {
+        // waves take hit tiles from a shared counter (tiles differ in work)
+        for (;;) {
+            int h = 0;
+            if (lane == 0)
+                h = atomicAdd(&s_next, 1);
+            h = __builtin_amdgcn_readfirstlane(__shfl(h, 0));
+            if (h >= nhit)
+                break;
             const int t = t0 + s_list[h];
             const int tx = t % tiles_x, ty = t / tiles_x;
             const int ix = tx * kTile + (lane & (kTile - 1));
@@ -505,24 +686,48 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                     const float s_af = readlane_f(af, c), s_bf = readlane_f(bf, c);
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
                     int *accs = acc + s_slot;
-                    for (int z = zbeg + lane; z < zend; z += 64) {
-                        const float val = colp[z];
-                        if constexpr (GEOM == kFan2D) {
-                            int *a = accs + (z - r0) * SW;
+                    if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
+                        if (sf_fast_ok(s_an, s_bn, s_af, s_bf, P.nz)) {
+                            float uw[K];
 #pragma unroll
                             for (int k = 0; k < K; ++k)
-                                if (k < s_nc)
-                                    atomicAdd(a + k, __float2int_rn(val * sw[k]));
-                        } else {
-                            const Trap tr = sf_axial(s_an, s_bn, s_af, s_bf, (float)z, P.eps);
-                            for_rows(tr, R, [&](int j, float F) {
-                                const float f = F * val;
-                                int *a = accs + j * SW;
+                                uw[k] = readlane_f(w[k], c);
+                            sf_column_fast<K>(colp, P.nz, s_an, s_bn, s_af, s_bf, qs, uw, s_nc,
+                                              accs, SW, R, cbuf, lane);
+                            continue;
+                        }
+                    }
+                    for (int zb = zbeg; zb < zend; zb += 256) {
+                        // issue the column's loads first, then compute
+                        float vals[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int z = zb + lane + 64 * q;
+                            vals[q] = z < zend ? colp[z] : 0.0f;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int z = zb + lane + 64 * q;
+                            if (z >= zend)
+                                break;
+                            const float val = vals[q];
+                            if constexpr (GEOM == kFan2D) {
+                                int *a = accs + (z - r0) * SW;
 #pragma unroll
                                 for (int k = 0; k < K; ++k)
                                     if (k < s_nc)
-                                        atomicAdd(a + k, __float2int_rn(f * sw[k]));
-                            });
+                                        atomicAdd(a + k, to_fixed(val * sw[k]));
+                            } else {
+                                const Trap tr = sf_axial(s_an, s_bn, s_af, s_bf, (float)z, P.eps);
+                                for_rows(tr, R, [&](int j, float F) {
+                                    const float f = F * val;
+                                    int *a = accs + j * SW;
+#pragma unroll
+                                    for (int k = 0; k < K; ++k)
+                                        if (k < s_nc)
+                                            atomicAdd(a + k, to_fixed(f * sw[k]));
+                                });
+                            }
                         }
                     }
                 }
@@ -563,7 +768,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
 #pragma unroll
                             for (int k = 0; k < K; ++k)
                                 if (k < nc)
-                                    atomicAdd(a + k, __float2int_rn(f * w[k]));
+                                    atomicAdd(a + k, to_fixed(f * w[k]));
                         });
                     }
                 }
@@ -590,14 +795,25 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                     }
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
                     int *accs = acc + s_slot;
-                    for (int z = zbeg + lane; z < zend; z += 64) {
-                        const float val = colp[z];
+                    for (int zb = zbeg; zb < zend; zb += 256) {
+                      float vals[4];
+#pragma unroll
+                      for (int q = 0; q < 4; ++q) {
+                          const int z = zb + lane + 64 * q;
+                          vals[q] = z < zend ? colp[z] : 0.0f;
+                      }
+#pragma unroll
+                      for (int q = 0; q < 4; ++q) {
+                        const int z = zb + lane + 64 * q;
+                        if (z >= zend)
+                            break;
+                        const float val = vals[q];
                         if constexpr (GEOM == kFan2D) {
                             int *a = accs + (z - r0) * SW;
 #pragma unroll
                             for (int k = 0; k < K; ++k)
                                 if (k < s_nc)
-                                    atomicAdd(a + k, __float2int_rn(val * sfx[k]));
+                                    atomicAdd(a + k, to_fixed(val * sfx[k]));
                         } else {
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
@@ -607,10 +823,11 @@ __global__ __launch_bounds__(256) void fwd_kernel(Params P, const ViewRec *__res
                                 const float zh = zl + sbe[k];
                                 const float vk = val * sfx[k];
                                 for_dd_rows(zl, zh, R, [&](int j, float wz) {
-                                    atomicAdd(accs + j * SW + k, __float2int_rn(vk * wz));
+                                    atomicAdd(accs + j * SW + k, to_fixed(vk * wz));
                                 });
                             }
                         }
+                      }
                     }
                 }
             }
@@ -642,11 +859,20 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles16_x = (P.nx + 15) >> 4;
-    const int T = blockIdx.x;
+    const int n_tiles = tiles16_x * ((P.ny + 15) >> 4);
+    const int n_items = n_tiles * ((P.nz + kZChunk - 1) / kZChunk);
+    // XCD-aware order: work-group i runs on XCD i % 8; each XCD takes a contiguous run of
+    // (z-chunk, tile) items, z-chunk major, so the work-groups sharing an XCD's L2 gather
+    // from the same few detector rows of each view.
+    const int per_xcd = (n_items + 7) >> 3;
+    const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if ((int)(blockIdx.x >> 3) >= per_xcd || item >= n_items)
+        return;
+    const int T = item % n_tiles;
     const int ix = (T % tiles16_x) * 16 + (wave & 1) * 8 + (lane & 7);
     const int iy = (T / tiles16_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
-    const int zc0 = blockIdx.y * kZChunk;
-    const int b = blockIdx.z;                 // batch item (3D); 0 in 2D
+    const int zc0 = (item / n_tiles) * kZChunk;
+    const int b = blockIdx.y;                 // batch item (3D); 0 in 2D
     const bool valid = ix < P.nx && iy < P.ny;
     const float xc = fmaf((float)ix, P.dx, P.x0), yc = fmaf((float)iy, P.dy, P.y0);
     const float hz = 0.5f * P.dz;
@@ -910,10 +1136,13 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
 {
     const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
     const int R = min(kRowsMax, rows_total);
-    const size_t lds = (size_t)R * (kStripW + 1) * sizeof(float);
+    size_t lds = (size_t)R * (kStripW + 1) * sizeof(int);
+    if (CTP_FWD_FAST && GEOM != kFan2D && METHOD == kSF)
+        lds += (size_t)kFwdWaves * (R + 1) * sizeof(unsigned);
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
-    dim3 grid(c.n_strips, p.n_views, (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks));
-    hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(256), lds, st, p, views,
+    dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.n_views),
+              (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
+    hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(kFwdThreads), lds, st, p, views,
                        volT, qscale, sino, accumulate, nchunks);
     return hipGetLastError();
 }
@@ -925,7 +1154,8 @@ hipError_t bwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
 {
     (void)c;
     const int tiles = ((p.nx + 15) / 16) * ((p.ny + 15) / 16);
-    dim3 grid(tiles, (p.nz + kZChunk - 1) / kZChunk, (unsigned)(GEOM == kFan2D ? 1 : batch));
+    const int items = tiles * ((p.nz + kZChunk - 1) / kZChunk);
+    dim3 grid((unsigned)(8 * ((items + 7) / 8)), (unsigned)(GEOM == kFan2D ? 1 : batch), 1);
     hipLaunchKernelGGL((bwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(256), 0, st, p, views,
                        ysc, vol, accumulate);
     return hipGetLastError();

@@ -425,7 +425,7 @@ ctp_status prepare_call(const ctp_plan *plan, const void *a, const void *b, ctp_
     const bool two_d = plan->g.kind == CTP_FAN2D;
     if (two_d && batch > (int64_t)1 << 24)
         return fail(CTP_EINVAL, "2D batch too large");
-    if (!two_d && batch > 65535)
+    if (!two_d && batch * plan->cfg.n_row_chunks > 65535)
         return fail(CTP_EINVAL, "batch too large");
     size_t need = 0;
     ctp_status st = ctp_workspace_bytes(plan, dir, batch, &need);
