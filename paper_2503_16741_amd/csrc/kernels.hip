@@ -23,10 +23,13 @@
 #include <hip/hip_runtime.h>
 
 #ifndef CTP_FWD_FAST
-#define CTP_FWD_FAST 0
+#define CTP_FWD_FAST 1
 #endif
 #ifndef CTP_CVT_TRUNC
 #define CTP_CVT_TRUNC 1
+#endif
+#ifndef CTP_BWD_FAST
+#define CTP_BWD_FAST 1
 #endif
 
 namespace ctp {
@@ -421,19 +424,18 @@ __device__ __forceinline__ void box_u_range(const ViewRec &V, const Params &P, f
 //
 // For a circular scan the v-projection of the face z = z_f of a voxel column is an interval
 // [p_f, q_f] whose ends are affine in f (nearest / farthest corner).  When consecutive faces'
-// intervals do not overlap, voxel z's SF-TT axial trapezoid rises over face z's interval, is
-// flat up to face z+1 and falls over face z+1's interval, so the column's axial profile
-// sum_z x_z trap_z(v) is piecewise linear and its integral C(t) up to row edge t is
-//   plateau of voxel z:  C(t) = S_z + x_z (w_z / 2 + t - q_z)
-//   inside face z:       C(t) = S_z - x_{z-1} (q_z - t)^2 / (2 w_z) + x_z (t - p_z)^2 / (2 w_z)
-// with S_z = sum_{z' < z} x_z' area_z' and area_z = mid_{z+1} - mid_z (mid: face centre).
-// Row j of the column receives C(j+1) - C(j) -- the same value as summing each voxel's
-// G(j+1) - G(j) -- so every row is touched once per column instead of once per voxel.
-// C is kept in 32-bit fixed point (scale qs) with wrapping arithmetic: the prefix S_z is an
-// exact integer scan, and row values are exact differences.
-// Lanes hold 4 consecutive voxels; each lane writes C at the row edges its voxels own into
-// the wavefront's LDS buffer cbuf[0..R]; then lanes run over rows and add the row value times
-// the column's transaxial weights to the strip.
+// intervals do not overlap, voxel z's SF-TT axial trapezoid rises over face z, is flat up to
+// face z+1 and falls over face z+1, so for any run of slices the integral of
+// sum_z x_z trap_z(v) up to row edge t is
+//   on voxel z's plateau:  C(t) = S_z + x_z (w_z / 2 + t - q_z)
+//   inside face z:         C(t) = S_z - x_{z-1} (q_z - t)^2 / (2 w_z) + x_z (t - p_z)^2 / (2 w_z)
+// (S_z: sum of x area over the run's slices below z, area_z = mid_{z+1} - mid_z, x_{z-1} = 0 at
+// the run's first face, and above the run's top face C is S minus the falling ramp).  Row j
+// gets C(j+1) - C(j), which equals the sum of the run's voxels' G(j+1) - G(j).  Runs are
+// independent (their contributions add), so each lane takes a run of 4 slices: neighbouring
+// lanes emit different rows at the same time, and no lane needs another lane's data.
+// C is kept in 32-bit fixed point (scale qs) with wrapping arithmetic; rows are exact
+// differences.
 __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float bf, int nz)
 {
     // faces z and z+1 disjoint for every z: an + bn z <= af + bf (z+1) and vice versa
@@ -445,17 +447,18 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 }
 
 template <int K>
-__device__ __forceinline__ void sf_column_fast(const float *__restrict__ colp, int nz, float an,
-                                               float bn, float af, float bf, float qs,
-                                               const float (&w)[K], int nc, int *accs, int SW,
-                                               int R, unsigned *cbuf, int lane)
+__device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
+                                           float bn, float af, float bf, float qs,
+                                           const float (&w)[K], int nc, int *accs, int SW,
+                                           int R, int lane)
 {
     const float fR = (float)R;
-    uint32_t carry = 0;       // S at the start of this 256-voxel chunk
     for (int zb = 0; zb < nz; zb += 256) {
         const int z0 = zb + 4 * lane;
+        if (z0 >= nz)
+            break;
         float v[4];
-        if ((nz & 3) == 0 && z0 + 3 < nz) {
+        if ((nz & 3) == 0) {
             const float4 v4 = *reinterpret_cast<const float4 *>(colp + z0);
             v[0] = v4.x; v[1] = v4.y; v[2] = v4.z; v[3] = v4.w;
         } else {
@@ -463,93 +466,132 @@ __device__ __forceinline__ void sf_column_fast(const float *__restrict__ colp, i
             for (int q = 0; q < 4; ++q)
                 v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
         }
+        const int nq = min(4, nz - z0);
         float p[5], qf[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            const float zf = (float)min(z0 + f, nz);
+            const float zf = (float)(z0 + min(f, nq));
             const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
             p[f] = fminf(vn, vf);
             qf[f] = fmaxf(vn, vf);
         }
-        uint32_t a[4], T = 0;
+        // skip runs entirely outside the row window
+        if (qf[nq] < 0.0f || p[0] >= fR)
+            continue;
+        int tp = max((int)floorf(p[0]), -1);     // last edge handled (C = 0 at floor(p0))
+        uint32_t Cprev = 0u, S = 0u;
+        float vm1 = 0.0f;
+        auto emit = [&](int t, uint32_t C) {
+            const int j = t - 1;
+            if (j >= 0) {
+                const float rv = (float)(int)(C - Cprev);
+                int *a = accs + j * SW;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k < nc)
+                        atomicAdd(a + k, to_fixed(rv * w[k]));
+            }
+            Cprev = C;
+        };
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float area = 0.5f * ((p[q + 1] + qf[q + 1]) - (p[q] + qf[q]));
-            a[q] = (uint32_t)__float2int_rn(v[q] * qs * area);
-            T += a[q];
-        }
-        // exclusive scan of the lane totals
-        uint32_t incl = T;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = (uint32_t)__shfl_up((int)incl, d);
-            if (lane >= d)
-                incl += o;
-        }
-        uint32_t S = carry + incl - T;
-        float vm1 = __shfl_up(v[3], 1);
-        if (lane == 0)
-            vm1 = zb > 0 ? colp[zb - 1] : 0.0f;   // voxel just below the chunk
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (z0 + q < nz) {
-                const int tb = max((int)ceilf(fmaxf(p[q], -1.0f)), 0);
-                const int te = min((int)ceilf(fminf(p[q + 1], fR + 1.0f)), R + 1);
-                const float wq = qf[q] - p[q];
-                for (int t = tb; t < te; ++t) {
+            if (q < nq) {
+                const float pz = p[q], qz = qf[q], wz = qz - pz;
+                const int te = min((int)ceilf(fminf(p[q + 1], fR + 1.0f)) - 1, R);
+                for (int t = tp + 1; t <= te; ++t) {
                     const float ft = (float)t;
                     float local;
-                    if (ft < qf[q] && wq > 1e-12f) {
-                        const float h = 0.5f * fast_rcp(wq);
-                        const float d1 = ft - p[q], d2 = qf[q] - ft;
+                    if (ft < qz && wz > 1e-12f) {
+                        const float h = 0.5f * fast_rcp(wz);
+                        const float d1 = ft - pz, d2 = qz - ft;
                         local = (v[q] * d1 * d1 - vm1 * d2 * d2) * h;
                     } else {
-                        local = v[q] * (0.5f * wq + (ft - qf[q]));
+                        local = v[q] * (0.5f * wz + (ft - qz));
                     }
-                    cbuf[t] = S + (uint32_t)__float2int_rn(local * qs);
+                    emit(t, S + (uint32_t)__float2int_rn(local * qs));
+                }
+                tp = max(tp, te);
+                const float area = 0.5f * ((p[q + 1] + qf[q + 1]) - (pz + qz));
+                S += (uint32_t)__float2int_rn(v[q] * qs * area);
+                vm1 = v[q];
+            }
+        }
+        // above the run's top face
+        {
+            const float pt = p[nq], qt = qf[nq], wt = qt - pt;
+            const int te = min((int)floorf(fminf(qt, fR)) + 1, R);
+            for (int t = tp + 1; t <= te; ++t) {
+                const float ft = (float)t;
+                float local = 0.0f;
+                if (ft < qt && wt > 1e-12f) {
+                    const float d2 = qt - ft;
+                    local = -vm1 * d2 * d2 * 0.5f * fast_rcp(wt);
+                }
+                emit(t, S + (uint32_t)__float2int_rn(local * qs));
+            }
+        }
+    }
+}
+
+
+// DD forward, circular: for column k of the footprint the slices' mapped z-intervals
+// [zeta_z, zeta_{z+1}] (rows, zeta_z = al_k + be_k z) tile the axis, so the run's integral up to
+// row edge t inside slice z is S_z + x_z (t - zeta_z) and row j gets C(j+1) - C(j) times the
+// column's transaxial fraction.  Same run-per-lane scheme as the SF path.
+template <int K>
+__device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int nz,
+                                           const float (&al)[K], const float (&be)[K],
+                                           const float (&fx)[K], int nc, float qs, int *accs,
+                                           int SW, int R, int lane)
+{
+    const float fR = (float)R;
+    for (int zb = 0; zb < nz; zb += 256) {
+        const int z0 = zb + 4 * lane;
+        if (z0 >= nz)
+            break;
+        float v[4];
+        if ((nz & 3) == 0) {
+            const float4 v4 = *reinterpret_cast<const float4 *>(colp + z0);
+            v[0] = v4.x; v[1] = v4.y; v[2] = v4.z; v[3] = v4.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
+        }
+        const int nq = min(4, nz - z0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k >= nc)
+                break;
+            float zt[5];
+#pragma unroll
+            for (int f = 0; f < 5; ++f)
+                zt[f] = fmaf(be[k], (float)(z0 + min(f, nq)), al[k]);
+            if (zt[nq] < 0.0f || zt[0] >= fR)
+                continue;
+            int tp = max((int)floorf(zt[0]), -1);
+            uint32_t Cprev = 0u, S = 0u;
+            int *ak = accs + k;
+            auto emit = [&](int t, uint32_t C) {
+                const int j = t - 1;
+                if (j >= 0)
+                    atomicAdd(ak + j * SW, to_fixed((float)(int)(C - Cprev) * fx[k]));
+                Cprev = C;
+            };
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < nq) {
+                    const int te = min((int)ceilf(fminf(zt[q + 1], fR + 1.0f)) - 1, R);
+                    for (int t = tp + 1; t <= te; ++t)
+                        emit(t, S + (uint32_t)__float2int_rn(v[q] * qs * ((float)t - zt[q])));
+                    tp = max(tp, te);
+                    S += (uint32_t)__float2int_rn(v[q] * qs * (zt[q + 1] - zt[q]));
                 }
             }
-            S += a[q];
-            vm1 = v[q];
+            const int te = min((int)floorf(fminf(zt[nq], fR)) + 1, R);
+            for (int t = tp + 1; t <= te; ++t)
+                emit(t, S);
         }
-        carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    }
-    const float vtop = colp[nz - 1];
-    // edges at and above the top face belong to the space above the column
-    {
-        const float zf = (float)nz;
-        const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
-        const float pt = fminf(vn, vf), qt = fmaxf(vn, vf), wt = qt - pt;
-        const int tb = max((int)ceilf(fmaxf(pt, -1.0f)), 0);
-        const int te = min((int)floorf(fminf(qt, fR)) + 1, R);       // inclusive
-        for (int t = tb + lane; t <= te; t += 64) {
-            const float ft = (float)t;
-            float local = 0.0f;
-            if (ft < qt && wt > 1e-12f) {
-                const float d2 = qt - ft;
-                local = -vtop * d2 * d2 * 0.5f * fast_rcp(wt);
-            }
-            cbuf[t] = carry + (uint32_t)__float2int_rn(local * qs);
-        }
-        // the edge just below the bottom face
-        const float vn0 = an, vf0 = af;
-        const float p0 = fminf(vn0, vf0);
-        const int tl = (int)floorf(fmaxf(p0, -1.0f));
-        if (lane == 0 && tl >= 0 && tl <= R && (float)tl < p0)
-            cbuf[tl] = 0u;
-        __builtin_amdgcn_wave_barrier();
-        // rows of the column inside [0, R)
-        const int jA = max(tl, 0);
-        const int jB = min((int)floorf(fminf(qt, fR)), R - 1);
-        for (int j = jA + lane; j <= jB; j += 64) {
-            const float rv = (float)(int)(cbuf[j + 1] - cbuf[j]);
-            int *a = accs + j * SW;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < nc)
-                    atomicAdd(a + k, __float2int_rn(rv * w[k]));
-        }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -597,8 +639,6 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     const ViewRec V = views[view];
     constexpr int SW = kStripW + 1;
 
-    // per-wavefront row-edge buffer of the fast path, after the accumulators
-    unsigned *cbuf = reinterpret_cast<unsigned *>(acc + R * SW) + wave * (R + 1);
     for (int e = threadIdx.x; e < R * SW; e += blockDim.x)
         acc[e] = 0;
     const float qs = qscale[0], qinv = qscale[1];
@@ -692,8 +732,8 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
 #pragma unroll
                             for (int k = 0; k < K; ++k)
                                 uw[k] = readlane_f(w[k], c);
-                            sf_column_fast<K>(colp, P.nz, s_an, s_bn, s_af, s_bf, qs, uw, s_nc,
-                                              accs, SW, R, cbuf, lane);
+                            sf_fwd_run<K>(colp, P.nz, s_an, s_bn, s_af, s_bf, qs, uw, s_nc,
+                                          accs, SW, R, lane);
                             continue;
                         }
                     }
@@ -795,6 +835,14 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     }
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
                     int *accs = acc + s_slot;
+                    if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
+                        float ufx[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            ufx[k] = readlane_f(fx[k], c);
+                        dd_fwd_run<K>(colp, P.nz, sal, sbe, ufx, s_nc, qs, accs, SW, R, lane);
+                        continue;
+                    }
                     for (int zb = zbeg; zb < zend; zb += 256) {
                       float vals[4];
 #pragma unroll
@@ -846,6 +894,84 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
         float *dst = sino + (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
                      (int64_t)j * P.sino_row_stride + i;
         *dst = accumulate ? *dst + val : val;
+    }
+}
+
+
+// ---- back projection fast path (circular SF) ----------------------------------------------
+//
+// Along one voxel column the projected faces [p_f, q_f] of consecutive slices are ordered and,
+// in the usual geometries, disjoint and narrower than a detector row.  Voxel z's SF-TT axial
+// trapezoid then rises over face z, is flat up to face z+1 and falls over face z+1, and its
+// gather sum_j F2_{z,j} r_j (r_j: the row's transaxially weighted sinogram value) equals
+// D(z+1) - D(z) with
+//   D(f) = R(q_f) - J_f,   R(t) = integral of r up to t,
+//   J_f  = integral over face f of r(v) (v - p_f) / w_f,  w_f = q_f - p_f.
+// A lane walks its kZChunk slices upwards, loading each detector row once (one row ahead),
+// keeping the running prefix of r and evaluating D once per face.
+__device__ __forceinline__ bool sf_bwd_fast_ok(float an, float bn, float af, float bf, int z0,
+                                               int z1)
+{
+    const float m = 1e-4f;
+    const float f0 = (float)z0, f1 = (float)z1;        // first and last voxel of the run
+    const float d0 = an - af, db = bn - bf;
+    const bool disjoint = bn > 1e-3f && bf > 1e-3f &&
+                          fmaf(db, f0, d0 - bf) <= -m && fmaf(db, f1, d0 - bf) <= -m &&
+                          fmaf(-db, f0, -d0 - bn) <= -m && fmaf(-db, f1, -d0 - bn) <= -m;
+    const bool narrow = fabsf(fmaf(db, f0, d0)) < 1.0f - m && fabsf(fmaf(db, f1 + 1.0f, d0)) < 1.0f - m;
+    return disjoint && narrow;
+}
+
+template <int K, int NQ>
+__device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_t row_stride,
+                                            int cs, int nu, int rows, const float (&w)[K],
+                                            float an, float bn, float af, float bf, int zc0,
+                                            int nq, float (&acc)[NQ])
+{
+    int cidx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        cidx[k] = min(cs + k, nu - 1);          // weights are 0 past the footprint
+    auto load_row = [&](int j) -> float {
+        float r = 0.0f;
+        if (j >= 0 && j < rows) {
+            const float *yr = yv + (int64_t)j * row_stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                r = fmaf(w[k], yr[cidx[k]], r);
+        }
+        return r;
+    };
+    const float fr = (float)rows;
+    const float zs = (float)zc0;
+    int jc = (int)floorf(fminf(fmaxf(fminf(fmaf(bn, zs, an), fmaf(bf, zs, af)), -1.0f), fr));
+    float rc = load_row(jc), rn = load_row(jc + 1), rp = 0.0f, RP = 0.0f, Dprev = 0.0f;
+#pragma unroll
+    for (int f = 0; f <= NQ; ++f) {
+        if (f <= nq) {
+            const float zf = (float)(zc0 + f);
+            const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
+            const float p = fminf(vn, vf), q = fmaxf(vn, vf), w = q - p;
+            const int jq = (int)floorf(fminf(fmaxf(q, -1.0f), fr));
+            while (jc < jq) {
+                RP += rc;
+                rp = rc;
+                rc = rn;
+                ++jc;
+                rn = load_row(jc + 1);
+            }
+            const float R = fmaf(q - (float)jc, rc, RP);
+            float J = 0.0f;
+            if (w > 1e-12f) {
+                const float a = (float)jc - p;              // > 0 when the face straddles row edge jc
+                const float h = 0.5f * fast_rcp(w);
+                J = a > 0.0f ? fmaf(rp - rc, a * a * h, rc * 0.5f * w) : rc * 0.5f * w;
+            }
+            const float D = R - J;
+            if (f > 0)
+                acc[f - 1] += D - Dprev;
+            Dprev = D;
+        }
     }
 }
 
@@ -919,6 +1045,12 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                 } else {
                     const float an = fmaf(col.An, zb0, V.cv), bn = col.An * P.dz;
                     const float af = fmaf(col.Af, zb0, V.cv), bf = col.Af * P.dz;
+                    const int nq = min(kZChunk, nzv - zc0);
+                    if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + nq - 1)) {
+                        sf_bwd_fast<K, kZChunk>(yv, P.sino_row_stride, cs, P.nu, rows_total, w,
+                                                an, bn, af, bf, zc0, nq, acc);
+                        continue;
+                    }
 #pragma unroll
                     for (int q = 0; q < kZChunk; ++q) {
                         const int z = zc0 + q;
@@ -1137,8 +1269,6 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
     const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
     const int R = min(kRowsMax, rows_total);
     size_t lds = (size_t)R * (kStripW + 1) * sizeof(int);
-    if (CTP_FWD_FAST && GEOM != kFan2D && METHOD == kSF)
-        lds += (size_t)kFwdWaves * (R + 1) * sizeof(unsigned);
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
     dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.n_views),
               (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
