@@ -51,7 +51,9 @@ typedef enum { CTP_FAN2D = 0, CTP_CONE_CIRC = 1, CTP_CONE_NONCIRC = 2 } ctp_geom
 typedef enum { CTP_DET_FLAT = 0, CTP_DET_CURVED = 1 } ctp_det;
 /* Projector models (Section 2.3). */
 typedef enum { CTP_SF = 0, CTP_DD = 1 } ctp_method;
-/* Storage types; only CTP_F32 is implemented. */
+/* Storage types of the caller's volume and sinogram buffers.  Arithmetic is FP32 in every
+ * case: BF16 / FP16 inputs are widened on load, outputs are rounded to nearest even on store
+ * (an FP16 value beyond 65504 becomes infinity). */
 typedef enum { CTP_F32 = 0, CTP_BF16 = 1, CTP_F16 = 2 } ctp_dtype;
 /* Direction of a call, for workspace queries. */
 typedef enum { CTP_FORWARD = 0, CTP_BACKWARD = 1 } ctp_direction;
@@ -98,29 +100,32 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
  * NULL is accepted. */
 ctp_status ctp_plan_destroy(ctp_plan *plan);
 
-/* Bytes of one volume and one sinogram for `batch` items in dtype (FP32 only). */
+/* Bytes of `batch` volumes and of `batch` sinograms stored as dtype. */
 ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch,
                           size_t *vol_bytes, size_t *sino_bytes);
 
-/* Device workspace (bytes) that ctp_project / ctp_backproject need for `batch` items:
- * forward: 256 bytes for the accumulator scale, one float per 32x32 tile of the volume for
- * its max |x|, and one z-fastest copy of the volume; backward: one copy of the sinogram
- * scaled by the per-cell amplitude (0 for 2D SF, which needs none).  The contents are
- * scratch: nothing is kept between calls. */
-ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t batch,
-                               size_t *bytes);
+/* Device workspace (bytes) that ctp_project (dir = CTP_FORWARD) or ctp_backproject
+ * (CTP_BACKWARD) needs for `batch` items with the given storage types.  Forward: 256 bytes
+ * for the accumulator scale, one float per 32x32 tile of the volume for its max |x|, one
+ * z-fastest FP32 copy of the volume, and an FP32 sinogram when the sinogram is BF16/FP16.
+ * Backward: an FP32 copy of the sinogram scaled by the per-cell amplitude (not needed for 2D
+ * SF with an FP32 sinogram), and an FP32 volume when the volume is BF16/FP16.  The contents
+ * are scratch; nothing is kept between calls. */
+ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, ctp_dtype vol_dtype,
+                               ctp_dtype sino_dtype, int64_t batch, size_t *bytes);
 
 /*
  * Forward projection (Eq. 1): sino = A vol, or sino += A vol when accumulate != 0.
  * vol, sino: device pointers in the layouts above, `batch` items (batch >= 1; the plan is
  * shared by all items, Section 1: batched, channelled tensors).  workspace: device pointer
- * of at least ctp_workspace_bytes(plan, CTP_FORWARD, batch) bytes, owned by the caller and
+ * of at least ctp_workspace_bytes(plan, CTP_FORWARD, vol_dtype, sino_dtype, batch) bytes,
+ * owned by the caller and
  * not used by any other concurrent call; 256-byte alignment required.  Asynchronous on
  * `stream` (0 = null stream); returns after enqueueing.
  * The volume must be finite: the projector accumulates in 32-bit fixed point whose scale is
  * set per call from max |vol| (relative resolution ~1e-9 of the largest possible cell sum).
- * Errors: CTP_EINVAL (NULL pointers, batch < 1, workspace too small or misaligned, plan used
- * on another device), CTP_EUNSUPPORTED (dtype other than CTP_F32), CTP_EDEVICE (launch).
+ * Errors: CTP_EINVAL (NULL pointers, batch < 1, unknown dtype, workspace too small or
+ * misaligned, plan used on another device), CTP_EDEVICE (launch).
  */
 ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype,
                        void *sino, ctp_dtype sino_dtype, int64_t batch, int accumulate,
@@ -129,7 +134,8 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
 /*
  * Back projection (Eq. 2), the exact transpose of ctp_project with the same weights:
  * vol = A^T sino, or vol += A^T sino when accumulate != 0.  Arguments as for ctp_project,
- * with the workspace sized by ctp_workspace_bytes(plan, CTP_BACKWARD, batch).
+ * with the workspace sized by ctp_workspace_bytes(plan, CTP_BACKWARD, vol_dtype, sino_dtype,
+ * batch).
  */
 ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype,
                            void *vol, ctp_dtype vol_dtype, int64_t batch, int accumulate,

@@ -73,12 +73,15 @@ struct LaunchCfg {
 };
 
 int64_t transpose_blocks(int64_t batch, int64_t nz, int64_t plane);
-hipError_t launch_transpose_zfast(const float *vol, float *volT, float *blockmax, int64_t batch,
-                                  int64_t nz, int64_t plane, hipStream_t st);
+// dtype: 0 = FP32, 1 = BF16, 2 = FP16 (storage type of the input / output buffer)
+hipError_t launch_transpose_zfast(const void *vol, int dtype, float *volT, float *blockmax,
+                                  int64_t batch, int64_t nz, int64_t plane, hipStream_t st);
+hipError_t launch_store_convert(const float *src, void *dst, int dtype, int64_t n, int accumulate,
+                                hipStream_t st);
 hipError_t launch_qscale(const float *blockmax, int64_t n, float bound, float *qscale,
                          hipStream_t st);
 hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *views,
-                            const float *sino, float *out, int64_t batch, hipStream_t st);
+                            const void *sino, int dtype, float *out, int64_t batch, hipStream_t st);
 hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,
                           const float *volT, const float *qscale, float *sino, int64_t batch,
                           int accumulate, hipStream_t st);

@@ -20,7 +20,11 @@
 // matched up to the order of the FP32 sums.
 #include "engine.h"
 
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #ifndef CTP_FWD_FAST
 #define CTP_FWD_FAST 1
@@ -34,6 +38,19 @@
 
 namespace ctp {
 namespace {
+
+// Storage types: BF16 / FP16 are converted to FP32 on load and rounded to nearest even on
+// store; all arithmetic is FP32.
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(__hip_bfloat16 v) { return __bfloat162float(v); }
+__device__ __forceinline__ float to_f32(__half v) { return __half2float(v); }
+template <typename T> __device__ __forceinline__ T from_f32(float v);
+template <> __device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ __hip_bfloat16 from_f32<__hip_bfloat16>(float v)
+{
+    return __float2bfloat16(v);
+}
+template <> __device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half(v); }
 
 // FP32 -> fixed point for the forward accumulators.  Truncation toward zero (one
 // instruction) biases each term by at most one unit of 2^-S; with the scale set so the
@@ -1174,8 +1191,9 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
 // ============================================================================================
 // Helpers: z-fastest copy of the volume, amplitude-scaled copy of the sinogram
 // ============================================================================================
-// z-fastest copy of the volume; also writes max |x| of each block to blockmax.
-__global__ __launch_bounds__(256) void transpose_zfast_kernel(const float *__restrict__ in,
+// z-fastest FP32 copy of the volume; also writes max |x| of each block to blockmax.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_zfast_kernel(const T *__restrict__ in,
                                                               float *__restrict__ out,
                                                               float *__restrict__ blockmax,
                                                               int64_t nz, int64_t plane)
@@ -1184,14 +1202,14 @@ __global__ __launch_bounds__(256) void transpose_zfast_kernel(const float *__res
     __shared__ float wmax[4];
     const int64_t b = blockIdx.z;
     const int64_t p0 = (int64_t)blockIdx.x * 32, z0 = (int64_t)blockIdx.y * 32;
-    const float *src = in + b * nz * plane;
+    const T *src = in + b * nz * plane;
     float *dst = out + b * nz * plane;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     float m = 0.0f;
     for (int r = ty; r < 32; r += 8) {
         const int64_t z = z0 + r, p = p0 + tx;
         if (z < nz && p < plane) {
-            const float v = src[z * plane + p];
+            const float v = to_f32(src[z * plane + p]);
             tile[r][tx] = v;
             m = fmaxf(m, fabsf(v));
         }
@@ -1242,9 +1260,9 @@ __global__ __launch_bounds__(1024) void qscale_kernel(const float *__restrict__ 
     }
 }
 
-template <int GEOM, int DET, int METHOD>
+template <int GEOM, int DET, int METHOD, typename T>
 __global__ __launch_bounds__(256) void amp_scale_kernel(Params P, const ViewRec *__restrict__ views,
-                                                        const float *__restrict__ in,
+                                                        const T *__restrict__ in,
                                                         float *__restrict__ out, int nrows)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -1255,7 +1273,7 @@ __global__ __launch_bounds__(256) void amp_scale_kernel(Params P, const ViewRec 
         return;
     const int64_t idx = (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
                         (int64_t)row * P.sino_row_stride + i;
-    out[idx] = in[idx] * cell_amp<GEOM, DET, METHOD>(views[view], P, i, row);
+    out[idx] = to_f32(in[idx]) * cell_amp<GEOM, DET, METHOD>(views[view], P, i, row);
     (void)nrows;
 }
 
@@ -1292,13 +1310,20 @@ hipError_t bwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
 }
 
 template <int GEOM, int DET, int METHOD>
-hipError_t amp_launch(const Params &p, const ViewRec *views, const float *in, float *out,
-                      int64_t batch, hipStream_t st)
+hipError_t amp_launch(const Params &p, const ViewRec *views, const void *in, int dtype,
+                      float *out, int64_t batch, hipStream_t st)
 {
     const int nrows = GEOM == kFan2D ? p.nz : p.nv;
     dim3 grid((p.nu + 255) / 256, nrows, (unsigned)(p.n_views * (GEOM == kFan2D ? 1 : batch)));
-    hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD>), grid, dim3(256), 0, st, p, views,
-                       in, out, nrows);
+    if (dtype == 1)
+        hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD, __hip_bfloat16>), grid, dim3(256), 0,
+                           st, p, views, (const __hip_bfloat16 *)in, out, nrows);
+    else if (dtype == 2)
+        hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD, __half>), grid, dim3(256), 0, st, p,
+                           views, (const __half *)in, out, nrows);
+    else
+        hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD, float>), grid, dim3(256), 0, st, p,
+                           views, (const float *)in, out, nrows);
     return hipGetLastError();
 }
 
@@ -1353,12 +1378,24 @@ struct BwdOp {
 
 template <int G, int D, int M, int K>
 struct AmpOp {
-    static hipError_t run(const Params &p, const ViewRec *views, const float *in, float *out,
-                          int64_t batch, hipStream_t st)
+    static hipError_t run(const Params &p, const ViewRec *views, const void *in, int dtype,
+                          float *out, int64_t batch, hipStream_t st)
     {
-        return amp_launch<G, D, M>(p, views, in, out, batch, st);
+        return amp_launch<G, D, M>(p, views, in, dtype, out, batch, st);
     }
 };
+
+// FP32 workspace -> BF16 / FP16 output (optionally accumulating into it).
+template <typename T>
+__global__ __launch_bounds__(256) void store_convert_kernel(const float *__restrict__ src,
+                                                            T *__restrict__ dst, int64_t n,
+                                                            int accumulate)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float v = src[i];
+        dst[i] = from_f32<T>(accumulate ? to_f32(dst[i]) + v : v);
+    }
+}
 
 }  // namespace
 
@@ -1367,12 +1404,34 @@ int64_t transpose_blocks(int64_t batch, int64_t nz, int64_t plane)
     return ((plane + 31) / 32) * ((nz + 31) / 32) * batch;
 }
 
-hipError_t launch_transpose_zfast(const float *vol, float *volT, float *blockmax, int64_t batch,
-                                  int64_t nz, int64_t plane, hipStream_t st)
+hipError_t launch_transpose_zfast(const void *vol, int dtype, float *volT, float *blockmax,
+                                  int64_t batch, int64_t nz, int64_t plane, hipStream_t st)
 {
     dim3 grid((unsigned)((plane + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)batch);
-    hipLaunchKernelGGL(transpose_zfast_kernel, grid, dim3(256), 0, st, vol, volT, blockmax, nz,
-                       plane);
+    if (dtype == 1)
+        hipLaunchKernelGGL(transpose_zfast_kernel<__hip_bfloat16>, grid, dim3(256), 0, st,
+                           (const __hip_bfloat16 *)vol, volT, blockmax, nz, plane);
+    else if (dtype == 2)
+        hipLaunchKernelGGL(transpose_zfast_kernel<__half>, grid, dim3(256), 0, st, (const __half *)vol,
+                           volT, blockmax, nz, plane);
+    else
+        hipLaunchKernelGGL(transpose_zfast_kernel<float>, grid, dim3(256), 0, st, (const float *)vol,
+                           volT, blockmax, nz, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_convert(const float *src, void *dst, int dtype, int64_t n, int accumulate,
+                                hipStream_t st)
+{
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    if (dtype == 1)
+        hipLaunchKernelGGL(store_convert_kernel<__hip_bfloat16>, dim3(blocks), dim3(256), 0, st, src,
+                           (__hip_bfloat16 *)dst, n, accumulate);
+    else if (dtype == 2)
+        hipLaunchKernelGGL(store_convert_kernel<__half>, dim3(blocks), dim3(256), 0, st, src,
+                           (__half *)dst, n, accumulate);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1384,11 +1443,11 @@ hipError_t launch_qscale(const float *blockmax, int64_t n, float bound, float *q
 }
 
 hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *views,
-                            const float *sino, float *out, int64_t batch, hipStream_t st)
+                            const void *sino, int dtype, float *out, int64_t batch, hipStream_t st)
 {
     LaunchCfg c4 = c;
     c4.kcells = 3;
-    return dispatch<AmpOp>(c4, p, views, sino, out, batch, st);
+    return dispatch<AmpOp>(c4, p, views, sino, dtype, out, batch, st);
 }
 
 hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,

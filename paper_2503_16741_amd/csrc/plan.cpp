@@ -353,16 +353,17 @@ ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch, 
     g_last_error.clear();
     if (plan == nullptr || batch < 1)
         return fail(CTP_EINVAL, "NULL plan or batch < 1");
-    if (dtype != CTP_F32)
-        return fail(CTP_EUNSUPPORTED, "only FP32 storage is implemented");
+    if (dtype != CTP_F32 && dtype != CTP_BF16 && dtype != CTP_F16)
+        return fail(CTP_EINVAL, "unknown dtype");
+    const size_t es = dtype == CTP_F32 ? 4 : 2;
     const ctp_geometry_desc &g = plan->g;
     const bool two_d = g.kind == CTP_FAN2D;
     const size_t nvox = (size_t)g.nx * g.ny * (two_d ? 1 : g.nz);
     const size_t ncell = (size_t)g.n_views * g.nu * (two_d ? 1 : g.nv);
     if (vol_bytes)
-        *vol_bytes = nvox * (size_t)batch * sizeof(float);
+        *vol_bytes = nvox * (size_t)batch * es;
     if (sino_bytes)
-        *sino_bytes = ncell * (size_t)batch * sizeof(float);
+        *sino_bytes = ncell * (size_t)batch * es;
     return CTP_OK;
 }
 
@@ -370,14 +371,20 @@ namespace {
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// Forward workspace: [0, 256) fixed-point scale, then the per-block max|x| of the transpose,
-// then the z-fastest copy of the volume.
+// Forward workspace: [0, 256) fixed-point scale, the per-block max|x| of the transpose, the
+// z-fastest FP32 copy of the volume, then (half-precision sinograms only) an FP32 sinogram.
+// Backward workspace: the amplitude-scaled FP32 sinogram (omitted for 2D SF with an FP32
+// sinogram), then (half-precision volumes only) an FP32 volume.
 struct FwdWs {
-    size_t blockmax_off, volT_off, total;
+    size_t blockmax_off, volT_off, sino_off, total;
     int64_t nblocks, tr_batch, tr_nz, plane;
 };
+struct BwdWs {
+    size_t ysc_off, vol_off, total;
+    bool scaled;
+};
 
-FwdWs fwd_ws_layout(const ctp_plan *plan, int64_t batch)
+FwdWs fwd_ws_layout(const ctp_plan *plan, int64_t batch, ctp_dtype sino_dtype)
 {
     const ctp_geometry_desc &g = plan->g;
     const bool two_d = g.kind == CTP_FAN2D;
@@ -388,24 +395,41 @@ FwdWs fwd_ws_layout(const ctp_plan *plan, int64_t batch)
     w.nblocks = ctp::transpose_blocks(w.tr_batch, w.tr_nz, w.plane);
     w.blockmax_off = 256;
     w.volT_off = w.blockmax_off + align256((size_t)w.nblocks * sizeof(float));
-    w.total = w.volT_off + (size_t)w.tr_batch * w.tr_nz * w.plane * sizeof(float);
+    w.sino_off = w.volT_off + align256((size_t)w.tr_batch * w.tr_nz * w.plane * sizeof(float));
+    size_t sb = 0;
+    ctp_plan_bytes(plan, CTP_F32, batch, nullptr, &sb);
+    w.total = w.sino_off + (sino_dtype == CTP_F32 ? 0 : sb);
+    return w;
+}
+
+BwdWs bwd_ws_layout(const ctp_plan *plan, int64_t batch, ctp_dtype vol_dtype, ctp_dtype sino_dtype)
+{
+    size_t vb = 0, sb = 0;
+    ctp_plan_bytes(plan, CTP_F32, batch, &vb, &sb);
+    BwdWs w;
+    w.scaled = !(plan->g.kind == CTP_FAN2D && plan->method == CTP_SF && sino_dtype == CTP_F32);
+    w.ysc_off = 0;
+    w.vol_off = w.scaled ? align256(sb) : 0;
+    w.total = w.vol_off + (vol_dtype == CTP_F32 ? 0 : vb);
     return w;
 }
 
 }  // namespace
 
-ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, int64_t batch, size_t *bytes)
+ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, ctp_dtype vol_dtype,
+                               ctp_dtype sino_dtype, int64_t batch, size_t *bytes)
 {
-    size_t vb = 0, sb = 0;
-    ctp_status st = ctp_plan_bytes(plan, CTP_F32, batch, &vb, &sb);
+    ctp_status st = ctp_plan_bytes(plan, vol_dtype, batch, nullptr, nullptr);
+    if (st == CTP_OK)
+        st = ctp_plan_bytes(plan, sino_dtype, batch, nullptr, nullptr);
     if (st != CTP_OK)
         return st;
     if (bytes == nullptr)
         return fail(CTP_EINVAL, "NULL output");
     if (dir == CTP_FORWARD)
-        *bytes = fwd_ws_layout(plan, batch).total;
+        *bytes = fwd_ws_layout(plan, batch, sino_dtype).total;
     else if (dir == CTP_BACKWARD)
-        *bytes = (plan->g.kind == CTP_FAN2D && plan->method == CTP_SF) ? 0 : sb;
+        *bytes = bwd_ws_layout(plan, batch, vol_dtype, sino_dtype).total;
     else
         return fail(CTP_EINVAL, "unknown direction");
     return CTP_OK;
@@ -420,15 +444,17 @@ ctp_status prepare_call(const ctp_plan *plan, const void *a, const void *b, ctp_
         return fail(CTP_EINVAL, "NULL plan or data pointer");
     if (batch < 1)
         return fail(CTP_EINVAL, "batch must be >= 1");
-    if (da != CTP_F32 || db != CTP_F32)
-        return fail(CTP_EUNSUPPORTED, "only FP32 storage is implemented");
+    for (ctp_dtype d : {da, db})
+        if (d != CTP_F32 && d != CTP_BF16 && d != CTP_F16)
+            return fail(CTP_EINVAL, "unknown dtype");
     const bool two_d = plan->g.kind == CTP_FAN2D;
     if (two_d && batch > (int64_t)1 << 24)
         return fail(CTP_EINVAL, "2D batch too large");
     if (!two_d && batch * plan->cfg.n_row_chunks > 65535)
         return fail(CTP_EINVAL, "batch too large");
     size_t need = 0;
-    ctp_status st = ctp_workspace_bytes(plan, dir, batch, &need);
+    const ctp_dtype vol_dt = dir == CTP_FORWARD ? da : db, sino_dt = dir == CTP_FORWARD ? db : da;
+    ctp_status st = ctp_workspace_bytes(plan, dir, vol_dt, sino_dt, batch, &need);
     if (st != CTP_OK)
         return st;
     if (need > 0 && (ws == nullptr || ws_bytes < need))
@@ -481,18 +507,25 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
                                  workspace_bytes, CTP_FORWARD, p);
     if (st != CTP_OK)
         return st;
-    const FwdWs w = fwd_ws_layout(plan, batch);
+    const FwdWs w = fwd_ws_layout(plan, batch, sino_dtype);
     char *ws = static_cast<char *>(workspace);
     float *qscale = reinterpret_cast<float *>(ws);
     float *blockmax = reinterpret_cast<float *>(ws + w.blockmax_off);
     float *volT = reinterpret_cast<float *>(ws + w.volT_off);
-    hipError_t e = ctp::launch_transpose_zfast((const float *)vol, volT, blockmax, w.tr_batch, w.tr_nz,
-                                               w.plane, stream);
+    const bool half_out = sino_dtype != CTP_F32;
+    float *out = half_out ? reinterpret_cast<float *>(ws + w.sino_off) : static_cast<float *>(sino);
+    hipError_t e = ctp::launch_transpose_zfast(vol, (int)vol_dtype, volT, blockmax, w.tr_batch,
+                                               w.tr_nz, w.plane, stream);
     if (e == hipSuccess)
         e = ctp::launch_qscale(blockmax, w.nblocks, plan->cfg.acc_bound, qscale, stream);
     if (e == hipSuccess)
-        e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, qscale, (float *)sino, batch,
-                                accumulate, stream);
+        e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, qscale, out, batch,
+                                half_out ? 0 : accumulate, stream);
+    if (e == hipSuccess && half_out) {
+        size_t sb = 0;
+        ctp_plan_bytes(plan, CTP_F32, batch, nullptr, &sb);
+        e = ctp::launch_store_convert(out, sino, (int)sino_dtype, (int64_t)(sb / 4), accumulate, stream);
+    }
     return finish(e, stream, "forward projection");
 }
 
@@ -506,14 +539,25 @@ ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sin
                                  workspace_bytes, CTP_BACKWARD, p);
     if (st != CTP_OK)
         return st;
-    const float *ys = (const float *)sino;
+    const BwdWs w = bwd_ws_layout(plan, batch, vol_dtype, sino_dtype);
+    char *ws = static_cast<char *>(workspace);
+    const float *ys = static_cast<const float *>(sino);
     hipError_t e = hipSuccess;
-    if (!(plan->g.kind == CTP_FAN2D && plan->method == CTP_SF)) {
-        e = ctp::launch_amp_scale(p, plan->cfg, plan->d_views, ys, (float *)workspace, batch, stream);
-        ys = (const float *)workspace;
+    if (w.scaled) {
+        e = ctp::launch_amp_scale(p, plan->cfg, plan->d_views, sino, (int)sino_dtype,
+                                  reinterpret_cast<float *>(ws + w.ysc_off), batch, stream);
+        ys = reinterpret_cast<const float *>(ws + w.ysc_off);
     }
+    const bool half_out = vol_dtype != CTP_F32;
+    float *out = half_out ? reinterpret_cast<float *>(ws + w.vol_off) : static_cast<float *>(vol);
     if (e == hipSuccess)
-        e = ctp::launch_backward(p, plan->cfg, plan->d_views, ys, (float *)vol, batch, accumulate, stream);
+        e = ctp::launch_backward(p, plan->cfg, plan->d_views, ys, out, batch,
+                                 half_out ? 0 : accumulate, stream);
+    if (e == hipSuccess && half_out) {
+        size_t vb = 0;
+        ctp_plan_bytes(plan, CTP_F32, batch, &vb, nullptr);
+        e = ctp::launch_store_convert(out, vol, (int)vol_dtype, (int64_t)(vb / 4), accumulate, stream);
+    }
     return finish(e, stream, "back projection");
 }
 

@@ -2,7 +2,8 @@
 
 Argument marshalling only: every step of the projection runs in the library's HIP kernels.
 The functions keep the C names; ``Plan`` owns a plan handle and frees it on ``close()``.
-Tensors passed in must be contiguous float32 CUDA (HIP) tensors; the current torch stream
+Tensors passed in must be contiguous CUDA (HIP) tensors of float32, bfloat16 or float16 (the
+storage type; arithmetic is always FP32); the current torch stream
 is used unless one is given.  If the library is not built the first call raises -- there is
 no CPU fallback.
 """
@@ -70,7 +71,8 @@ def lib() -> ctypes.CDLL:
             L.ctp_plan_create.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.POINTER(vp)]
             L.ctp_plan_destroy.argtypes = [vp]
             L.ctp_plan_bytes.argtypes = [vp, ctypes.c_int, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)]
-            L.ctp_workspace_bytes.argtypes = [vp, ctypes.c_int, i64, ctypes.POINTER(sz)]
+            L.ctp_workspace_bytes.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, i64,
+                                              ctypes.POINTER(sz)]
             L.ctp_project.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i64, ctypes.c_int,
                                       vp, sz, vp]
             L.ctp_backproject.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i64, ctypes.c_int,
@@ -167,11 +169,20 @@ def ctp_plan_bytes(plan: Plan, batch: int = 1, dtype: int = CTP_F32):
     return vb.value, sb.value
 
 
-def ctp_workspace_bytes(plan: Plan, direction: int, batch: int = 1) -> int:
+def ctp_workspace_bytes(plan: Plan, direction: int, batch: int = 1, vol_dtype: int = CTP_F32,
+                        sino_dtype: int = CTP_F32) -> int:
     b = ctypes.c_size_t()
-    _check(lib().ctp_workspace_bytes(plan.handle, direction, batch, ctypes.byref(b)),
-           "ctp_workspace_bytes")
+    _check(lib().ctp_workspace_bytes(plan.handle, direction, vol_dtype, sino_dtype, batch,
+                                     ctypes.byref(b)), "ctp_workspace_bytes")
     return b.value
+
+
+def _dtype_code(t) -> int:
+    import torch
+    codes = {torch.float32: CTP_F32, torch.bfloat16: CTP_BF16, torch.float16: CTP_F16}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported dtype {t.dtype}: use float32, bfloat16 or float16")
+    return codes[t.dtype]
 
 
 def _stream_handle(stream) -> int:
@@ -181,11 +192,12 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def _workspace(plan: Plan, direction: int, batch: int, device):
+def _workspace(plan: Plan, direction: int, batch: int, device, vol_dtype=CTP_F32,
+               sino_dtype=CTP_F32):
     """A cached, 256-byte-aligned workspace tensor for this plan/direction/batch (torch
     allocations are 512-byte aligned)."""
     import torch
-    need = ctp_workspace_bytes(plan, direction, batch)
+    need = ctp_workspace_bytes(plan, direction, batch, vol_dtype, sino_dtype)
     if need == 0:
         return None, 0
     key = (direction, str(device))
@@ -200,8 +212,9 @@ def _check_tensor(t, shape, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-    if t.dtype != torch.float32 or not t.is_contiguous():
-        raise TypeError(f"{name} must be contiguous float32")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    _dtype_code(t)
     if tuple(t.shape[-len(shape):]) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [...]+{tuple(shape)}")
 
@@ -215,11 +228,12 @@ def ctp_project(plan: Plan, vol, sino, accumulate: bool = False, workspace=None,
     batch = vol.numel() // int(np.prod(g.vol_shape))
     if sino.numel() != batch * int(np.prod(g.sino_shape)):
         raise ValueError("vol and sino batch sizes differ")
+    vd, sd = _dtype_code(vol), _dtype_code(sino)
     if workspace is None:
-        ws, nbytes = _workspace(plan, CTP_FORWARD, batch, vol.device)
+        ws, nbytes = _workspace(plan, CTP_FORWARD, batch, vol.device, vd, sd)
     else:
         ws, nbytes = workspace, workspace.numel() * workspace.element_size()
-    _check(lib().ctp_project(plan.handle, vol.data_ptr(), CTP_F32, sino.data_ptr(), CTP_F32,
+    _check(lib().ctp_project(plan.handle, vol.data_ptr(), vd, sino.data_ptr(), sd,
                              batch, int(bool(accumulate)),
                              ws.data_ptr() if ws is not None else None, nbytes,
                              _stream_handle(stream)), "ctp_project")
@@ -235,30 +249,33 @@ def ctp_backproject(plan: Plan, sino, vol, accumulate: bool = False, workspace=N
     batch = vol.numel() // int(np.prod(g.vol_shape))
     if sino.numel() != batch * int(np.prod(g.sino_shape)):
         raise ValueError("vol and sino batch sizes differ")
+    vd, sd = _dtype_code(vol), _dtype_code(sino)
     if workspace is None:
-        ws, nbytes = _workspace(plan, CTP_BACKWARD, batch, vol.device)
+        ws, nbytes = _workspace(plan, CTP_BACKWARD, batch, vol.device, vd, sd)
     else:
         ws, nbytes = workspace, workspace.numel() * workspace.element_size()
-    _check(lib().ctp_backproject(plan.handle, sino.data_ptr(), CTP_F32, vol.data_ptr(), CTP_F32,
+    _check(lib().ctp_backproject(plan.handle, sino.data_ptr(), sd, vol.data_ptr(), vd,
                                  batch, int(bool(accumulate)),
                                  ws.data_ptr() if ws is not None else None, nbytes,
                                  _stream_handle(stream)), "ctp_backproject")
     return vol
 
 
-def project(plan: Plan, vol):
-    """Convenience: allocate the sinogram and forward-project."""
+def project(plan: Plan, vol, out_dtype=None):
+    """Convenience: allocate the sinogram (same storage type as vol unless given) and
+    forward-project."""
     import torch
     g = plan.geom
     lead = tuple(vol.shape[:vol.dim() - len(g.vol_shape)])
-    sino = torch.empty(lead + tuple(g.sino_shape), dtype=torch.float32, device=vol.device)
+    sino = torch.empty(lead + tuple(g.sino_shape), dtype=out_dtype or vol.dtype, device=vol.device)
     return ctp_project(plan, vol, sino)
 
 
-def backproject(plan: Plan, sino):
-    """Convenience: allocate the volume and back-project."""
+def backproject(plan: Plan, sino, out_dtype=None):
+    """Convenience: allocate the volume (same storage type as sino unless given) and
+    back-project."""
     import torch
     g = plan.geom
     lead = tuple(sino.shape[:sino.dim() - len(g.sino_shape)])
-    vol = torch.empty(lead + tuple(g.vol_shape), dtype=torch.float32, device=sino.device)
+    vol = torch.empty(lead + tuple(g.vol_shape), dtype=out_dtype or sino.dtype, device=sino.device)
     return ctp_backproject(plan, sino, vol)

@@ -77,4 +77,18 @@ def test_null_arguments(ct):
     assert lib.ctp_project(None, None, 0, None, 0, 1, 0, None, 0, None) == ct.CTP_EINVAL
     assert lib.ctp_backproject(None, None, 0, None, 0, 1, 0, None, 0, None) == ct.CTP_EINVAL
     n = ctypes.c_size_t()
-    assert lib.ctp_workspace_bytes(None, 0, 1, ctypes.byref(n)) == ct.CTP_EINVAL
+    assert lib.ctp_workspace_bytes(None, 0, 0, 0, 1, ctypes.byref(n)) == ct.CTP_EINVAL
+
+
+def test_projector_module_arguments():
+    """Projector(geom, mode, method, direction) validates its strings without a device."""
+    from paper_2503_16741_amd.autograd import Projector
+    g = geom()
+    with pytest.raises(NotImplementedError):
+        Projector(g, "recon", "SF", "forward")
+    with pytest.raises(NotImplementedError):
+        Projector(g, "proj", "VD", "forward")
+    with pytest.raises(ValueError):
+        Projector(g, "proj", "SF", "sideways")
+    p = Projector(g, "proj", "dd", "backward")
+    assert p.method == "dd" and p.direction == "backward"

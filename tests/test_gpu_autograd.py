@@ -94,5 +94,5 @@ def test_mbir_descent(torch_gpu):
         loss = wls_loss(A, x, y_hat, w)
         loss.backward()
         opt.step()
-        losses.append(float(loss))
+        losses.append(loss.item())
     assert losses[-1] < 0.2 * losses[0]
