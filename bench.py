@@ -140,6 +140,129 @@ def cpu_baseline(geom, vol, n_views=128, n_vox=1500000):
                       f"({updates:.3e} voxel-view updates in {secs:.1f} s)"}
 
 
+def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, seed=0):
+    """Serving under Poisson arrivals: requests drawn uniformly from the ladder (2D fan 256^2 and
+    3D cone 128^3 / 256^3 / 384^3, 400 views) x {forward, back} x {FP32, BF16}, submitted to the
+    serving engine at `load` times the rate one device sustains when the requests run one after
+    another; latency = completion - submission on the server's clock."""
+    import queue
+    import threading
+    import numpy as np
+    import torch
+    from paper_2503_16741_amd import ctproj, synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ladder = synth.serving_ladder()
+    geoms = dict(ladder)
+    plans = {n: ctproj.ctp_plan_create(g, "sf") for n, g in ladder}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    inputs = {}
+    for n, g in ladder:
+        for d in ("forward", "backward"):
+            for dt in (torch.float32, torch.bfloat16):
+                shape = g.vol_shape if d == "forward" else g.sino_shape
+                inputs[(n, d, dt)] = torch.rand(shape, generator=gen, device=dev).to(dt)
+    classes = list(inputs)
+    vv = {c: float(geoms[c[0]].n_vox) * geoms[c[0]].n_views for c in classes}
+
+    def alone(c):
+        plan, x = plans[c[0]], inputs[c]
+        return ctproj.project(plan, x) if c[1] == "forward" else ctproj.backproject(plan, x)
+
+    svc = {}
+    for c in classes:
+        alone(c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            alone(c)
+        e1.record()
+        torch.cuda.synchronize()
+        svc[c] = e0.elapsed_time(e1) / 2
+    mean_svc = float(np.mean([svc[c] for c in classes]))
+    capacity = 1000.0 / mean_svc
+    alone_gups = sum(vv.values()) / (sum(svc.values()) * 1e-3) / 1e9
+    print(f"[serving] mean service time alone {mean_svc:.2f} ms -> {capacity:.1f} req/s; "
+          f"alone throughput {alone_gups:.1f} GUPS", file=sys.stderr, flush=True)
+
+    srv = ctproj.Server(int(arena_gb * (1 << 30)), n_slots=n_slots, max_batch=max_batch)
+    results = []
+    rng = np.random.default_rng(seed + 1)
+    for load in loads:
+        lam = load * capacity
+        gaps = rng.exponential(1.0 / lam, size=int(lam * seconds * 2) + 16)
+        arrivals = np.cumsum(gaps)
+        arrivals = arrivals[arrivals < seconds]
+        picks = rng.integers(len(classes), size=len(arrivals))
+        done_q = queue.Queue()
+        records = []
+
+        def collect():
+            while True:
+                item = done_q.get()
+                if item is None:
+                    return
+                t, c = item
+                srv.wait(t)
+                records.append((c, srv.info(t)))
+                srv.release(t)
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for a, k in zip(arrivals, picks):
+            dt = t0 + a - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            c = classes[int(k)]
+            done_q.put((srv.submit(plans[c[0]], c[1], inputs[c]), c))
+        done_q.put(None)
+        th.join()
+        lat = np.array([(i["done_ns"] - i["submit_ns"]) * 1e-6 for _, i in records])
+        t_first = min(i["submit_ns"] for _, i in records)
+        t_last = max(i["done_ns"] for _, i in records)
+        gups = sum(vv[c] for c, _ in records) / ((t_last - t_first) * 1e-9) / 1e9
+        per = {}
+        for n, _ in ladder:
+            l = np.array([(i["done_ns"] - i["submit_ns"]) * 1e-6 for c, i in records if c[0] == n])
+            if len(l):
+                per[n] = {"n": int(len(l)), "p50_ms": round(float(np.percentile(l, 50)), 3),
+                          "p99_ms": round(float(np.percentile(l, 99)), 3)}
+        batches = np.array([i["batch"] for _, i in records])
+        r = {"load": load, "lambda_per_s": round(lam, 2), "n_requests": int(len(records)),
+             "gups": round(gups, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+             "mean_batch": round(float(batches.mean()), 3), "per_class": per}
+        print(f"[serving] load {load}: {r['n_requests']} requests, {r['gups']} GUPS, "
+              f"p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms", file=sys.stderr, flush=True)
+        results.append(r)
+    st = srv.stats()
+    srv.close()
+    top = results[-1]
+    out = {"metric": "serving: GUPS and p50/p99 latency under Poisson arrivals (continuous batching)",
+           "value": top["gups"], "unit": "GUPS", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32+bf16 storage, f32 arithmetic", "data": "synthetic",
+           "config": {"workload": "SF forward / back projection requests drawn uniformly from "
+                                  "2D fan 256^2 (360 views, 512 x 1 mm) and 3D circular cone "
+                                  "128^3 / 256^3 / 384^3 at 0.4 mm (400 views, flat 640x480 at "
+                                  "0.6 mm), FP32 or BF16, 50/50 forward/back",
+                      "arena_gb": arena_gb, "n_slots": n_slots, "max_batch": max_batch,
+                      "seconds_per_load": seconds},
+           "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+           "alone": {"gups": round(alone_gups, 2), "mean_service_ms": round(mean_svc, 3),
+                     "capacity_req_per_s": round(capacity, 2),
+                     "service_ms": {f"{c[0]}/{c[1]}/{str(c[2]).split('.')[-1]}": round(v, 3)
+                                    for c, v in svc.items()}},
+           "loads": results,
+           "server": {"calls": st["calls"], "max_running": st["max_running"],
+                      "max_batch_seen": st["max_batch_seen"],
+                      "arena_peak_gb": round(st["arena_peak"] / (1 << 30), 3)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +274,13 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB device copy, one SF forward and one SF back projection "
                          "(for FETCH_SIZE / WRITE_SIZE counter runs) and exit")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving benchmark (Poisson arrivals of mixed requests) instead")
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--serving-loads", default="0.7,0.8,0.9")
+    ap.add_argument("--serving-arena-gb", type=float, default=32.0)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-max-batch", type=int, default=8)
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
@@ -160,6 +290,11 @@ def main():
               "(views would shard with no exchange; the adjoint needs one all-reduce)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        serving_bench(args.serving_seconds, [float(v) for v in args.serving_loads.split(",")],
+                      args.serving_arena_gb, args.serving_slots, args.serving_max_batch)
+        return
 
     import numpy as np
     import torch

@@ -42,7 +42,8 @@ typedef enum {
     CTP_EINVAL = -1,        /* bad argument, size or geometry (e.g. object at/behind source) */
     CTP_EUNSUPPORTED = -2,  /* valid request that this build does not implement */
     CTP_ENOMEM = -3,        /* device or host allocation failed */
-    CTP_EDEVICE = -4        /* HIP runtime / launch failure */
+    CTP_EDEVICE = -4,       /* HIP runtime / launch failure */
+    CTP_ETIMEOUT = -5       /* a wait ended before the work was done (ctserve.h) */
 } ctp_status;
 
 /* Scan kinds (Section 2.2). */
@@ -105,9 +106,10 @@ ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch,
                           size_t *vol_bytes, size_t *sino_bytes);
 
 /* Device workspace (bytes) that ctp_project (dir = CTP_FORWARD) or ctp_backproject
- * (CTP_BACKWARD) needs for `batch` items with the given storage types.  Forward: 256 bytes
- * for the accumulator scale, one float per 32x32 tile of the volume for its max |x|, one
- * z-fastest FP32 copy of the volume, and an FP32 sinogram when the sinogram is BF16/FP16.
+ * (CTP_BACKWARD) needs for `batch` items with the given storage types.  Forward: two floats
+ * per item for its accumulator scale, one float per 8192-element block of each item for its
+ * max |x|, one z-fastest FP32 copy of the volume, and an FP32 sinogram when the sinogram is
+ * BF16/FP16 (each part rounded up to 256 bytes).
  * Backward: an FP32 copy of the sinogram scaled by the per-cell amplitude (not needed for 2D
  * SF with an FP32 sinogram), and an FP32 volume when the volume is BF16/FP16.  The contents
  * are scratch; nothing is kept between calls. */
@@ -123,7 +125,9 @@ ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, ctp_dtyp
  * not used by any other concurrent call; 256-byte alignment required.  Asynchronous on
  * `stream` (0 = null stream); returns after enqueueing.
  * The volume must be finite: the projector accumulates in 32-bit fixed point whose scale is
- * set per call from max |vol| (relative resolution ~1e-9 of the largest possible cell sum).
+ * set per batch item from that item's max |vol| (relative resolution ~1e-9 of the largest
+ * possible cell sum; items with max |vol| * footprint bound below ~2^-96 lose resolution).  An
+ * item's result therefore does not depend on the other items of the batch.
  * Errors: CTP_EINVAL (NULL pointers, batch < 1, unknown dtype, workspace too small or
  * misaligned, plan used on another device), CTP_EDEVICE (launch).
  */

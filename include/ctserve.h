@@ -1,0 +1,106 @@
+/*
+ * ctserve.h -- C ABI of the projector serving engine (continuous batching on one device).
+ *
+ * A server accepts forward (A x) and back projection (A^T y) requests for any number of plans
+ * (ctproj.h) as they arrive, and runs them on one device while others are still running:
+ *
+ *   - Memory.  The caller hands the server one device arena (its HBM budget).  Every admitted
+ *     call takes from it the outputs of its requests, the workspace of the call
+ *     (ctp_workspace_bytes) and, when several requests are merged, a staging copy of their
+ *     inputs.  A request is admitted only when that footprint fits in the free arena; until
+ *     then it waits in the queue.  Outputs stay resident in the arena until released.
+ *   - Batching.  When a slot is free the oldest queued request is admitted together with the
+ *     later queued requests that share its plan, direction and storage types (at most
+ *     max_batch; the paper's batched, channelled tensors, Section 1 and 2.4: one plan serves the
+ *     whole batch).  If the merged call does not fit, fewer requests are merged; the oldest
+ *     request is always the next to run (first come, first served).
+ *   - Overlap.  Each slot owns a HIP stream; up to n_slots calls run concurrently.
+ *
+ * Results are those of ctp_project / ctp_backproject with batch = the merged count.  Every
+ * batch item's result is bitwise independent of the other items of its call (the forward
+ * projector's fixed-point scale is chosen per item, the back projector is a per-voxel gather),
+ * so a request gets the same bits alone and in the mix.
+ *
+ * The server runs one host thread of its own, which polls the slots' completion events while
+ * calls are in flight (one busy host core) and sleeps when the server is idle.
+ * All functions return a ctp_status; ctp_last_error() holds the detail.
+ */
+#ifndef CTSERVE_H
+#define CTSERVE_H
+
+#include "ctproj.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ctp_server ctp_server;   /* opaque */
+
+typedef struct {
+    void *arena;          /* device memory on the current device, 256-byte aligned, owned by the
+                             caller and unused by it while the server lives */
+    size_t arena_bytes;   /* the HBM budget */
+    int32_t n_slots;      /* concurrent calls (streams), 1..16 */
+    int32_t max_batch;    /* most requests merged into one call, 1..1024 */
+} ctp_server_config;
+
+/* Host-clock times (steady clock, ns) and placement of one request. */
+typedef struct {
+    int64_t submit_ns;    /* ctp_server_submit returned */
+    int64_t admit_ns;     /* its call was launched */
+    int64_t done_ns;      /* the server saw its call complete */
+    int32_t batch;        /* requests in its call */
+    int32_t slot;         /* stream slot of its call */
+} ctp_request_info;
+
+typedef struct {
+    int64_t submitted, completed, failed, calls;
+    int32_t max_running;  /* most calls in flight at once */
+    int32_t max_batch_seen;
+    size_t arena_peak;    /* most arena bytes in use at once */
+} ctp_server_stats;
+
+/* Start a server on the current device.  Errors: CTP_EINVAL (NULL config or arena, sizes out of
+ * range, misaligned arena), CTP_EDEVICE (stream / event creation), CTP_ENOMEM. */
+ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out);
+
+/* Queue one request: out = A in (dir = CTP_FORWARD, in is one volume) or out = A^T in
+ * (CTP_BACKWARD, in is one sinogram), layouts as in ctproj.h, batch 1.  `input` is device memory
+ * that must stay valid and unchanged until the request completes; `ready` is the stream whose
+ * work so far produces it (the server's call waits for it; 0 = the null stream).  The plan must
+ * outlive the request and belong to the server's device.  Returns at once with a ticket (> 0).
+ * Errors: CTP_EINVAL (NULL arguments, unknown direction or dtype, plan of another device),
+ * CTP_ENOMEM (the request alone can never fit in the arena), CTP_EDEVICE. */
+ctp_status ctp_server_submit(ctp_server *srv, const ctp_plan *plan, ctp_direction dir,
+                             const void *input, ctp_dtype in_dtype, ctp_dtype out_dtype,
+                             hipStream_t ready, uint64_t *ticket);
+
+/* Wait until the request is done (timeout_us < 0: no limit).  On success *result (if not NULL)
+ * is the device address of its output inside the arena, complete and valid until released.
+ * Errors: CTP_EINVAL (unknown or released ticket), CTP_ETIMEOUT (not done within timeout_us;
+ * the request goes on), or the status of its failed call (CTP_EINVAL / CTP_EDEVICE, with the
+ * call's message). */
+ctp_status ctp_server_wait(ctp_server *srv, uint64_t ticket, int64_t timeout_us, void **result);
+
+/* Non-blocking: *done = 1 and *result set when complete, else *done = 0. */
+ctp_status ctp_server_query(ctp_server *srv, uint64_t ticket, int *done, void **result);
+
+/* Times and placement of a request (valid until it is released). */
+ctp_status ctp_server_info(ctp_server *srv, uint64_t ticket, ctp_request_info *info);
+
+/* Give the request's output back to the arena.  `consumer` is the stream on which the caller's
+ * last use of the output was enqueued: the memory is reused only after that work has run.
+ * A queued or running request cannot be released (CTP_EINVAL); the ticket is forgotten. */
+ctp_status ctp_server_release(ctp_server *srv, uint64_t ticket, hipStream_t consumer);
+
+ctp_status ctp_server_get_stats(ctp_server *srv, ctp_server_stats *stats);
+
+/* Wait for every queued and running request, then stop the thread and free the streams and
+ * events.  The arena is not freed (it is the caller's).  NULL is accepted. */
+ctp_status ctp_server_destroy(ctp_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTSERVE_H */

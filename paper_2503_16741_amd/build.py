@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libctproj.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("plan.cpp", "kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("plan.cpp", "server.cpp", "kernels.hip")]
 ARCH = os.environ.get("CTP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

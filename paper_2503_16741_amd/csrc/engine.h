@@ -7,7 +7,16 @@
 #include <cstddef>
 #include <cstdint>
 
+#include <string>
+
+#include "../../include/ctproj.h"
+
 namespace ctp {
+
+// Error reporting and plan access shared by the ABI entry points (plan.cpp).
+ctp_status set_error(ctp_status st, const std::string &msg);
+void clear_error();
+int plan_device(const ctp_plan *plan);
 
 enum Geom : int { kFan2D = 0, kCirc = 1, kNonCirc = 2 };
 enum Det : int { kFlat = 0, kCurved = 1 };
@@ -72,14 +81,21 @@ struct LaunchCfg {
     float acc_bound;   // bound on a detector cell's pre-amplitude sum per unit |x|
 };
 
-int64_t transpose_blocks(int64_t batch, int64_t nz, int64_t plane);
-// dtype: 0 = FP32, 1 = BF16, 2 = FP16 (storage type of the input / output buffer)
-hipError_t launch_transpose_zfast(const void *vol, int dtype, float *volT, float *blockmax,
-                                  int64_t batch, int64_t nz, int64_t plane, hipStream_t st);
+// Per-item fixed-point scale of the forward projector.  dtype: 0 = FP32, 1 = BF16, 2 = FP16
+// (storage type of the input / output buffer).  An item is a contiguous span of item_elems
+// elements; blockmax holds item_max_blocks(item_elems) floats per item, qscale two per item.
+int item_max_blocks(int64_t item_elems);
+hipError_t launch_item_max(const void *vol, int dtype, int64_t n_items, int64_t item_elems,
+                           float *blockmax, hipStream_t st);
+hipError_t launch_qscale(const float *blockmax, int64_t n_items, int bpi, float bound,
+                         float *qscale, hipStream_t st);
+// z-fastest FP32 copy of `batch` volumes of nz x plane, scaled by the item's 2^S (item = b, or
+// item = z when item_is_z).
+hipError_t launch_transpose_zfast(const void *vol, int dtype, float *volT, const float *qscale,
+                                  int64_t batch, int64_t nz, int64_t plane, int item_is_z,
+                                  hipStream_t st);
 hipError_t launch_store_convert(const float *src, void *dst, int dtype, int64_t n, int accumulate,
                                 hipStream_t st);
-hipError_t launch_qscale(const float *blockmax, int64_t n, float bound, float *qscale,
-                         hipStream_t st);
 hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *views,
                             const void *sino, int dtype, float *out, int64_t batch, hipStream_t st);
 hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,

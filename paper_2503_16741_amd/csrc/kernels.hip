@@ -451,8 +451,8 @@ __device__ __forceinline__ void box_u_range(const ViewRec &V, const Params &P, f
 // gets C(j+1) - C(j), which equals the sum of the run's voxels' G(j+1) - G(j).  Runs are
 // independent (their contributions add), so each lane takes a run of 4 slices: neighbouring
 // lanes emit different rows at the same time, and no lane needs another lane's data.
-// C is kept in 32-bit fixed point (scale qs) with wrapping arithmetic; rows are exact
-// differences.
+// C is kept in 32-bit fixed point (the column values arrive pre-scaled by the item's 2^S)
+// with wrapping arithmetic; rows are exact differences.
 __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float bf, int nz)
 {
     // faces z and z+1 disjoint for every z: an + bn z <= af + bf (z+1) and vice versa
@@ -465,7 +465,7 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 
 template <int K>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
-                                           float bn, float af, float bf, float qs,
+                                           float bn, float af, float bf,
                                            const float (&w)[K], int nc, int *accs, int SW,
                                            int R, int lane)
 {
@@ -525,11 +525,11 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                     } else {
                         local = v[q] * (0.5f * wz + (ft - qz));
                     }
-                    emit(t, S + (uint32_t)__float2int_rn(local * qs));
+                    emit(t, S + (uint32_t)__float2int_rn(local));
                 }
                 tp = max(tp, te);
                 const float area = 0.5f * ((p[q + 1] + qf[q + 1]) - (pz + qz));
-                S += (uint32_t)__float2int_rn(v[q] * qs * area);
+                S += (uint32_t)__float2int_rn(v[q] * area);
                 vm1 = v[q];
             }
         }
@@ -544,7 +544,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                     const float d2 = qt - ft;
                     local = -vm1 * d2 * d2 * 0.5f * fast_rcp(wt);
                 }
-                emit(t, S + (uint32_t)__float2int_rn(local * qs));
+                emit(t, S + (uint32_t)__float2int_rn(local));
             }
         }
     }
@@ -558,7 +558,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
 template <int K>
 __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int nz,
                                            const float (&al)[K], const float (&be)[K],
-                                           const float (&fx)[K], int nc, float qs, int *accs,
+                                           const float (&fx)[K], int nc, int *accs,
                                            int SW, int R, int lane)
 {
     const float fR = (float)R;
@@ -600,9 +600,9 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
                 if (q < nq) {
                     const int te = min((int)ceilf(fminf(zt[q + 1], fR + 1.0f)) - 1, R);
                     for (int t = tp + 1; t <= te; ++t)
-                        emit(t, S + (uint32_t)__float2int_rn(v[q] * qs * ((float)t - zt[q])));
+                        emit(t, S + (uint32_t)__float2int_rn(v[q] * ((float)t - zt[q])));
                     tp = max(tp, te);
-                    S += (uint32_t)__float2int_rn(v[q] * qs * (zt[q + 1] - zt[q]));
+                    S += (uint32_t)__float2int_rn(v[q] * (zt[q + 1] - zt[q]));
                 }
             }
             const int te = min((int)floorf(fminf(zt[nq], fR)) + 1, R);
@@ -628,10 +628,11 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                                                   int n_row_chunks)
 {
     // Fixed-point accumulators: on gfx950 an LDS integer add costs a few cycles per
-    // wavefront while the FP32 LDS atomic is far slower.  Contributions are scaled by
-    // 2^S (qscale[0], chosen per call from max |x| so the strip sums fit in 31 bits) and
-    // rounded to nearest; integer sums are also order independent, so the result is
-    // bitwise repeatable.
+    // wavefront while the FP32 LDS atomic is far slower.  The z-fastest volume copy holds
+    // x * 2^S with S chosen per batch item from that item's max |x| (so its strip sums fit in
+    // 31 bits); contributions are converted to integers and summed, which is order
+    // independent, so an item's result is bitwise repeatable and does not depend on the
+    // other items of the batch.  qscale[2 b + 1] = 2^-S undoes the scale on write-out.
     extern __shared__ int acc[];             // [R][kStripW + 1]
     __shared__ int s_count, s_next;
     __shared__ unsigned short s_list[kListCap];
@@ -658,7 +659,6 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
 
     for (int e = threadIdx.x; e < R * SW; e += blockDim.x)
         acc[e] = 0;
-    const float qs = qscale[0], qinv = qscale[1];
 
     const float hz = 0.5f * P.dz;
     const float zb0 = P.z0 - hz - V.s[2];               // bottom face of slice 0, minus z_src
@@ -738,19 +738,15 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     float sw[K];
 #pragma unroll
                     for (int k = 0; k < K; ++k)
-                        sw[k] = readlane_f(w[k], c) * qs;
+                        sw[k] = readlane_f(w[k], c);
                     const float s_an = readlane_f(an, c), s_bn = readlane_f(bn, c);
                     const float s_af = readlane_f(af, c), s_bf = readlane_f(bf, c);
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
                         if (sf_fast_ok(s_an, s_bn, s_af, s_bf, P.nz)) {
-                            float uw[K];
-#pragma unroll
-                            for (int k = 0; k < K; ++k)
-                                uw[k] = readlane_f(w[k], c);
-                            sf_fwd_run<K>(colp, P.nz, s_an, s_bn, s_af, s_bf, qs, uw, s_nc,
-                                          accs, SW, R, lane);
+                            sf_fwd_run<K>(colp, P.nz, s_an, s_bn, s_af, s_bf, sw, s_nc, accs,
+                                          SW, R, lane);
                             continue;
                         }
                     }
@@ -818,7 +814,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                         float w[K];
                         sf_cell_weights<K>(cc, cs, nc, P.eps, w);
                         int *accs = acc + (cs - i_lo);
-                        const float vq = val * qs;
+                        const float vq = val;
                         for_rows(vx.ax, R, [&](int j, float F) {
                             const float f = F * vq;
                             int *a = accs + j * SW;
@@ -845,7 +841,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     float sfx[K], sal[K], sbe[K];
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        sfx[k] = readlane_f(fx[k], c) * qs;
+                        sfx[k] = readlane_f(fx[k], c);
                         const float bk = readlane_f(bz[k], c);
                         sal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
                         sbe[k] = bk * P.dz;
@@ -853,11 +849,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
-                        float ufx[K];
-#pragma unroll
-                        for (int k = 0; k < K; ++k)
-                            ufx[k] = readlane_f(fx[k], c);
-                        dd_fwd_run<K>(colp, P.nz, sal, sbe, ufx, s_nc, qs, accs, SW, R, lane);
+                        dd_fwd_run<K>(colp, P.nz, sal, sbe, sfx, s_nc, accs, SW, R, lane);
                         continue;
                     }
                     for (int zb = zbeg; zb < zend; zb += 256) {
@@ -907,6 +899,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
         if (i >= i_hi)
             continue;
         const int j = r0 + row;
+        const float qinv = qscale[2 * (GEOM == kFan2D ? j : b) + 1];
         const float val = (float)acc[row * SW + k] * qinv * cell_amp<GEOM, DET, METHOD>(V, P, i, j);
         float *dst = sino + (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
                      (int64_t)j * P.sino_row_stride + i;
@@ -1191,72 +1184,92 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
 // ============================================================================================
 // Helpers: z-fastest copy of the volume, amplitude-scaled copy of the sinogram
 // ============================================================================================
-// z-fastest FP32 copy of the volume; also writes max |x| of each block to blockmax.
+// max |x| of each block of one batch item: grid (blocks per item, items); an item is the
+// contiguous span of item_elems elements (a volume in 3D, an image in 2D).
+template <typename T>
+__global__ __launch_bounds__(256) void item_max_kernel(const T *__restrict__ in, int64_t n_items,
+                                                       int64_t item_elems,
+                                                       float *__restrict__ blockmax)
+{
+    __shared__ float wmax[4];
+    for (int64_t item = blockIdx.y; item < n_items; item += gridDim.y) {
+        const T *src = in + item * item_elems;
+        float m = 0.0f;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < item_elems;
+             i += (int64_t)gridDim.x * 256)
+            m = fmaxf(m, fabsf(to_f32(src[i])));
+        for (int off = 32; off > 0; off >>= 1)
+            m = fmaxf(m, __shfl_xor(m, off));
+        __syncthreads();          // wmax of the previous item has been read
+        if ((threadIdx.x & 63) == 0)
+            wmax[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            blockmax[item * gridDim.x + blockIdx.x] =
+                fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    }
+}
+
+// Fixed-point scale of one item's forward accumulators (block = item): 2^S with S the largest
+// integer such that max|x| * bound * 2^S <= 2^30 (bound: largest possible pre-amplitude sum per
+// detector cell per unit density), qscale[2 item] = 2^S, qscale[2 item + 1] = 2^-S.  A zero or
+// non-finite maximum gives S = 0.
+__global__ __launch_bounds__(256) void qscale_kernel(const float *__restrict__ blockmax,
+                                                     int64_t n_items, int bpi, float bound,
+                                                     float *__restrict__ qscale)
+{
+    __shared__ float red[4];
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const float *bm = blockmax + item * bpi;
+        float m = 0.0f;
+        for (int i = threadIdx.x; i < bpi; i += 256)
+            m = fmaxf(m, bm[i]);
+        for (int off = 32; off > 0; off >>= 1)
+            m = fmaxf(m, __shfl_xor(m, off));
+        __syncthreads();          // red of the previous item has been read
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+            int S = 0;
+            const float top = m * bound;
+            if (top > 0.0f && isfinite(top)) {
+                S = (int)floorf(30.0f - log2f(top));
+                S = max(-126, min(S, 126));
+            }
+            qscale[2 * item] = ldexpf(1.0f, S);
+            qscale[2 * item + 1] = ldexpf(1.0f, -S);
+        }
+    }
+}
+
+// z-fastest FP32 copy of the volume, each value multiplied by its item's 2^S (a power of two:
+// exact).  The item is the batch index b (3D) or the "z" index itself (2D, where the batch
+// takes the place of the axial dimension).
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_zfast_kernel(const T *__restrict__ in,
                                                               float *__restrict__ out,
-                                                              float *__restrict__ blockmax,
-                                                              int64_t nz, int64_t plane)
+                                                              const float *__restrict__ qscale,
+                                                              int64_t nz, int64_t plane,
+                                                              int item_is_z)
 {
     __shared__ float tile[32][33];
-    __shared__ float wmax[4];
     const int64_t b = blockIdx.z;
     const int64_t p0 = (int64_t)blockIdx.x * 32, z0 = (int64_t)blockIdx.y * 32;
     const T *src = in + b * nz * plane;
     float *dst = out + b * nz * plane;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    float m = 0.0f;
     for (int r = ty; r < 32; r += 8) {
         const int64_t z = z0 + r, p = p0 + tx;
-        if (z < nz && p < plane) {
-            const float v = to_f32(src[z * plane + p]);
-            tile[r][tx] = v;
-            m = fmaxf(m, fabsf(v));
-        }
+        if (z < nz && p < plane)
+            tile[r][tx] = to_f32(src[z * plane + p]);
     }
-    for (int off = 32; off > 0; off >>= 1)
-        m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0)
-        wmax[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        blockmax[blk] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-    }
     for (int r = ty; r < 32; r += 8) {
         const int64_t p = p0 + r, z = z0 + tx;
         if (z < nz && p < plane)
-            dst[p * nz + z] = tile[tx][r];
-    }
-}
-
-// Fixed-point scale of the forward accumulators: 2^S with S the largest integer such that
-// max|x| * bound * 2^S <= 2^30 (bound: largest possible pre-amplitude sum per detector cell
-// per unit density).  qscale = {2^S, 2^-S}.
-__global__ __launch_bounds__(1024) void qscale_kernel(const float *__restrict__ blockmax,
-                                                      int64_t n, float bound,
-                                                      float *__restrict__ qscale)
-{
-    __shared__ float red[16];
-    float m = 0.0f;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
-        m = fmaxf(m, blockmax[i]);
-    for (int off = 32; off > 0; off >>= 1)
-        m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-            m = fmaxf(m, red[w]);
-        int S = 0;
-        const float top = m * bound;
-        if (top > 0.0f && isfinite(top)) {
-            S = (int)floorf(30.0f - log2f(top));
-            S = max(-100, min(S, 100));
-        }
-        qscale[0] = ldexpf(1.0f, S);
-        qscale[1] = ldexpf(1.0f, -S);
+            dst[p * nz + z] = tile[tx][r] * qscale[2 * (item_is_z ? z : b)];
     }
 }
 
@@ -1399,24 +1412,41 @@ __global__ __launch_bounds__(256) void store_convert_kernel(const float *__restr
 
 }  // namespace
 
-int64_t transpose_blocks(int64_t batch, int64_t nz, int64_t plane)
+int item_max_blocks(int64_t item_elems)
 {
-    return ((plane + 31) / 32) * ((nz + 31) / 32) * batch;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((item_elems + 8191) / 8192, 1024));
 }
 
-hipError_t launch_transpose_zfast(const void *vol, int dtype, float *volT, float *blockmax,
-                                  int64_t batch, int64_t nz, int64_t plane, hipStream_t st)
+hipError_t launch_item_max(const void *vol, int dtype, int64_t n_items, int64_t item_elems,
+                           float *blockmax, hipStream_t st)
+{
+    dim3 grid((unsigned)item_max_blocks(item_elems), (unsigned)std::min<int64_t>(n_items, 65535));
+    if (dtype == 1)
+        hipLaunchKernelGGL(item_max_kernel<__hip_bfloat16>, grid, dim3(256), 0, st,
+                           (const __hip_bfloat16 *)vol, n_items, item_elems, blockmax);
+    else if (dtype == 2)
+        hipLaunchKernelGGL(item_max_kernel<__half>, grid, dim3(256), 0, st, (const __half *)vol,
+                           n_items, item_elems, blockmax);
+    else
+        hipLaunchKernelGGL(item_max_kernel<float>, grid, dim3(256), 0, st, (const float *)vol,
+                           n_items, item_elems, blockmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_zfast(const void *vol, int dtype, float *volT, const float *qscale,
+                                  int64_t batch, int64_t nz, int64_t plane, int item_is_z,
+                                  hipStream_t st)
 {
     dim3 grid((unsigned)((plane + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)batch);
     if (dtype == 1)
         hipLaunchKernelGGL(transpose_zfast_kernel<__hip_bfloat16>, grid, dim3(256), 0, st,
-                           (const __hip_bfloat16 *)vol, volT, blockmax, nz, plane);
+                           (const __hip_bfloat16 *)vol, volT, qscale, nz, plane, item_is_z);
     else if (dtype == 2)
         hipLaunchKernelGGL(transpose_zfast_kernel<__half>, grid, dim3(256), 0, st, (const __half *)vol,
-                           volT, blockmax, nz, plane);
+                           volT, qscale, nz, plane, item_is_z);
     else
         hipLaunchKernelGGL(transpose_zfast_kernel<float>, grid, dim3(256), 0, st, (const float *)vol,
-                           volT, blockmax, nz, plane);
+                           volT, qscale, nz, plane, item_is_z);
     return hipGetLastError();
 }
 
@@ -1435,10 +1465,11 @@ hipError_t launch_store_convert(const float *src, void *dst, int dtype, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_qscale(const float *blockmax, int64_t n, float bound, float *qscale,
-                         hipStream_t st)
+hipError_t launch_qscale(const float *blockmax, int64_t n_items, int bpi, float bound,
+                         float *qscale, hipStream_t st)
 {
-    hipLaunchKernelGGL(qscale_kernel, dim3(1), dim3(1024), 0, st, blockmax, n, bound, qscale);
+    hipLaunchKernelGGL(qscale_kernel, dim3((unsigned)std::min<int64_t>(n_items, 65535)), dim3(256), 0,
+                       st, blockmax, n_items, bpi, bound, qscale);
     return hipGetLastError();
 }
 

@@ -111,6 +111,12 @@ Mat3 pose(double th, double ph, double ps)
 
 }  // namespace
 
+namespace ctp {
+ctp_status set_error(ctp_status st, const std::string &msg) { return fail(st, msg); }
+void clear_error() { g_last_error.clear(); }
+int plan_device(const ctp_plan *plan) { return plan->device; }
+}  // namespace ctp
+
 extern "C" {
 
 const char *ctp_status_string(ctp_status s)
@@ -121,6 +127,7 @@ const char *ctp_status_string(ctp_status s)
     case CTP_EUNSUPPORTED: return "unsupported";
     case CTP_ENOMEM: return "out of memory";
     case CTP_EDEVICE: return "device error";
+    case CTP_ETIMEOUT: return "timed out";
     }
     return "unknown status";
 }
@@ -371,13 +378,15 @@ namespace {
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// Forward workspace: [0, 256) fixed-point scale, the per-block max|x| of the transpose, the
-// z-fastest FP32 copy of the volume, then (half-precision sinograms only) an FP32 sinogram.
+// Forward workspace: the per-item fixed-point scales (two floats per batch item), the per-block
+// max |x| of each item, the z-fastest scaled FP32 copy of the volume, then (half-precision
+// sinograms only) an FP32 sinogram.
 // Backward workspace: the amplitude-scaled FP32 sinogram (omitted for 2D SF with an FP32
 // sinogram), then (half-precision volumes only) an FP32 volume.
 struct FwdWs {
     size_t blockmax_off, volT_off, sino_off, total;
-    int64_t nblocks, tr_batch, tr_nz, plane;
+    int64_t item_elems, tr_batch, tr_nz, plane;
+    int bpi;
 };
 struct BwdWs {
     size_t ysc_off, vol_off, total;
@@ -392,9 +401,10 @@ FwdWs fwd_ws_layout(const ctp_plan *plan, int64_t batch, ctp_dtype sino_dtype)
     w.plane = (int64_t)g.nx * g.ny;
     w.tr_batch = two_d ? 1 : batch;
     w.tr_nz = two_d ? batch : g.nz;
-    w.nblocks = ctp::transpose_blocks(w.tr_batch, w.tr_nz, w.plane);
-    w.blockmax_off = 256;
-    w.volT_off = w.blockmax_off + align256((size_t)w.nblocks * sizeof(float));
+    w.item_elems = two_d ? w.plane : w.plane * g.nz;
+    w.bpi = ctp::item_max_blocks(w.item_elems);
+    w.blockmax_off = align256((size_t)batch * 2 * sizeof(float));
+    w.volT_off = w.blockmax_off + align256((size_t)batch * w.bpi * sizeof(float));
     w.sino_off = w.volT_off + align256((size_t)w.tr_batch * w.tr_nz * w.plane * sizeof(float));
     size_t sb = 0;
     ctp_plan_bytes(plan, CTP_F32, batch, nullptr, &sb);
@@ -514,10 +524,12 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
     float *volT = reinterpret_cast<float *>(ws + w.volT_off);
     const bool half_out = sino_dtype != CTP_F32;
     float *out = half_out ? reinterpret_cast<float *>(ws + w.sino_off) : static_cast<float *>(sino);
-    hipError_t e = ctp::launch_transpose_zfast(vol, (int)vol_dtype, volT, blockmax, w.tr_batch,
-                                               w.tr_nz, w.plane, stream);
+    hipError_t e = ctp::launch_item_max(vol, (int)vol_dtype, batch, w.item_elems, blockmax, stream);
     if (e == hipSuccess)
-        e = ctp::launch_qscale(blockmax, w.nblocks, plan->cfg.acc_bound, qscale, stream);
+        e = ctp::launch_qscale(blockmax, batch, w.bpi, plan->cfg.acc_bound, qscale, stream);
+    if (e == hipSuccess)
+        e = ctp::launch_transpose_zfast(vol, (int)vol_dtype, volT, qscale, w.tr_batch, w.tr_nz,
+                                        w.plane, plan->g.kind == CTP_FAN2D ? 1 : 0, stream);
     if (e == hipSuccess)
         e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, qscale, out, batch,
                                 half_out ? 0 : accumulate, stream);

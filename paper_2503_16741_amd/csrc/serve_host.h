@@ -1,0 +1,128 @@
+// serve_host.h -- host-only parts of the serving engine (no HIP): the device-arena allocator
+// and the choice of the requests merged into one call.  Kept free of HIP so that they can be
+// compiled and tested with a plain C++ compiler.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <iterator>
+#include <map>
+#include <vector>
+
+namespace ctp {
+
+// First-fit allocator over [0, size) in 256-byte units.  Offsets only: the caller adds them to
+// the base of its device arena.  Free blocks are coalesced with their neighbours.
+class Arena {
+public:
+    static constexpr size_t kAlign = 256;
+    static constexpr size_t kFail = SIZE_MAX;
+
+    void reset(size_t bytes)
+    {
+        size_ = bytes & ~(kAlign - 1);
+        free_.clear();
+        used_.clear();
+        in_use_ = peak_ = 0;
+        if (size_ > 0)
+            free_[0] = size_;
+    }
+
+    static size_t round_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
+
+    // Lowest-address free block that holds `bytes` (rounded up to 256); kFail if none.
+    // Zero bytes are allocated as one 256-byte unit so that every allocation has an address.
+    size_t alloc(size_t bytes)
+    {
+        const size_t n = round_up(bytes == 0 ? 1 : bytes);
+        if (n < bytes)
+            return kFail;   // overflow
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n)
+                continue;
+            const size_t off = it->first, rest = it->second - n;
+            free_.erase(it);
+            if (rest > 0)
+                free_[off + n] = rest;
+            used_[off] = n;
+            in_use_ += n;
+            if (in_use_ > peak_)
+                peak_ = in_use_;
+            return off;
+        }
+        return kFail;
+    }
+
+    // Returns false for an offset that is not a live allocation.
+    bool release(size_t off)
+    {
+        auto u = used_.find(off);
+        if (u == used_.end())
+            return false;
+        size_t start = off, n = u->second;
+        used_.erase(u);
+        in_use_ -= n;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + n) {
+            n += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                n += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = n;
+        return true;
+    }
+
+    size_t size() const { return size_; }
+    size_t in_use() const { return in_use_; }
+    size_t peak() const { return peak_; }
+    size_t largest_free() const
+    {
+        size_t m = 0;
+        for (const auto &f : free_)
+            m = f.second > m ? f.second : m;
+        return m;
+    }
+    size_t n_free_blocks() const { return free_.size(); }
+
+private:
+    size_t size_ = 0, in_use_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+    std::map<size_t, size_t> used_;   // offset -> bytes
+};
+
+// Requests that may share one call: same plan, direction and storage types.
+struct BatchKey {
+    const void *plan;
+    int dir, in_dtype, out_dtype;
+    bool operator==(const BatchKey &o) const
+    {
+        return plan == o.plan && dir == o.dir && in_dtype == o.in_dtype && out_dtype == o.out_dtype;
+    }
+};
+
+// Positions in `queue` (oldest first) of the requests merged with the oldest one: the head and
+// then, in arrival order, later requests with the same key, at most max_batch in all.  The
+// head is always served first (first come, first served); requests of other keys keep their
+// places.  `key_of` maps a queue element to its BatchKey.
+template <typename T, typename KeyOf>
+std::vector<size_t> batch_candidates(const std::deque<T> &queue, int max_batch, KeyOf key_of)
+{
+    std::vector<size_t> pos;
+    if (queue.empty() || max_batch < 1)
+        return pos;
+    const BatchKey head = key_of(queue.front());
+    for (size_t i = 0; i < queue.size() && (int)pos.size() < max_batch; ++i)
+        if (key_of(queue[i]) == head)
+            pos.push_back(i);
+    return pos;
+}
+
+}  // namespace ctp

@@ -21,7 +21,7 @@ from .synth import Geometry, PER_VIEW
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctproj.so")
 
-CTP_OK, CTP_EINVAL, CTP_EUNSUPPORTED, CTP_ENOMEM, CTP_EDEVICE = 0, -1, -2, -3, -4
+CTP_OK, CTP_EINVAL, CTP_EUNSUPPORTED, CTP_ENOMEM, CTP_EDEVICE, CTP_ETIMEOUT = 0, -1, -2, -3, -4, -5
 CTP_FAN2D, CTP_CONE_CIRC, CTP_CONE_NONCIRC = 0, 1, 2
 CTP_DET_FLAT, CTP_DET_CURVED = 0, 1
 CTP_SF, CTP_DD = 0, 1
@@ -34,6 +34,10 @@ METHOD = {"sf": CTP_SF, "dd": CTP_DD}
 
 EXPORTED = ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes", "ctp_workspace_bytes",
             "ctp_project", "ctp_backproject", "ctp_status_string", "ctp_last_error")
+# include/ctserve.h
+EXPORTED_SERVER = ("ctp_server_create", "ctp_server_submit", "ctp_server_wait",
+                   "ctp_server_query", "ctp_server_info", "ctp_server_release",
+                   "ctp_server_get_stats", "ctp_server_destroy")
 
 
 class CtpError(RuntimeError):
@@ -51,6 +55,23 @@ class _Desc(ctypes.Structure):
                  ("n_views", ctypes.c_int32)]
                 + [(n, ctypes.POINTER(ctypes.c_double)) for n in PER_VIEW]
                 + [("len_" + n, ctypes.c_int32) for n in PER_VIEW])
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("batch", ctypes.c_int32), ("slot", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("calls", ctypes.c_int64),
+                ("max_running", ctypes.c_int32), ("max_batch_seen", ctypes.c_int32),
+                ("arena_peak", ctypes.c_size_t)]
 
 
 _lib = None
@@ -79,6 +100,19 @@ def lib() -> ctypes.CDLL:
                                           vp, sz, vp]
             for f in ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes",
                       "ctp_workspace_bytes", "ctp_project", "ctp_backproject"):
+                getattr(L, f).restype = ctypes.c_int
+            u64 = ctypes.c_uint64
+            L.ctp_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+            L.ctp_server_submit.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
+                                            vp, ctypes.POINTER(u64)]
+            L.ctp_server_wait.argtypes = [vp, u64, i64, ctypes.POINTER(vp)]
+            L.ctp_server_query.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(vp)]
+            L.ctp_server_info.argtypes = [vp, u64, ctypes.POINTER(_RequestInfo)]
+            L.ctp_server_release.argtypes = [vp, u64, vp]
+            L.ctp_server_get_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+            L.ctp_server_destroy.argtypes = [vp]
+            for f in EXPORTED_SERVER:
                 getattr(L, f).restype = ctypes.c_int
             L.ctp_status_string.argtypes = [ctypes.c_int]
             L.ctp_status_string.restype = ctypes.c_char_p
@@ -279,3 +313,107 @@ def backproject(plan: Plan, sino, out_dtype=None):
     lead = tuple(sino.shape[:sino.dim() - len(g.sino_shape)])
     vol = torch.empty(lead + tuple(g.vol_shape), dtype=out_dtype or sino.dtype, device=sino.device)
     return ctp_backproject(plan, sino, vol)
+
+
+# ---- serving engine (include/ctserve.h) ------------------------------------------------------
+
+
+def _torch_dtype(code: int):
+    import torch
+    return {CTP_F32: torch.float32, CTP_BF16: torch.bfloat16, CTP_F16: torch.float16}[code]
+
+
+class Server:
+    """Owner of a ``ctp_server*`` and of the device arena it sub-allocates (its HBM budget).
+
+    ``submit`` queues a request and returns its ticket; ``wait`` returns the output as a tensor
+    view into the arena (valid until ``release``).  The input tensor is kept referenced until its
+    request has finished.
+    """
+
+    def __init__(self, arena_bytes: int, n_slots: int = 4, max_batch: int = 16, device=None):
+        import torch
+        self.device = torch.device(device or "cuda")
+        # uint8 arena; torch's allocations are at least 256-byte aligned
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        cfg = _ServerConfig(self.arena.data_ptr(), int(arena_bytes), int(n_slots), int(max_batch))
+        out = ctypes.c_void_p()
+        _check(lib().ctp_server_create(ctypes.byref(cfg), ctypes.byref(out)), "ctp_server_create")
+        self.handle = out
+        self._pending = {}     # ticket -> (input tensor, plan, out dtype code, out shape)
+
+    def submit(self, plan: Plan, direction: str, x, out_dtype=None, stream=None) -> int:
+        """Queue ``A x`` (direction 'forward', x one volume) or ``A^T x`` ('backward', x one
+        sinogram).  x must be a contiguous device tensor of one item."""
+        g = plan.geom
+        fwd = direction == "forward"
+        if not fwd and direction != "backward":
+            raise ValueError("direction must be 'forward' or 'backward'")
+        shape_in = g.vol_shape if fwd else g.sino_shape
+        _check_tensor(x, shape_in, "input")
+        if x.numel() != int(np.prod(shape_in)):
+            raise ValueError("a request holds exactly one item")
+        in_code = _dtype_code(x)
+        out_code = in_code if out_dtype is None else _dtype_code_of(out_dtype)
+        t = ctypes.c_uint64()
+        _check(lib().ctp_server_submit(self.handle, plan.handle, CTP_FORWARD if fwd else CTP_BACKWARD,
+                                       x.data_ptr(), in_code, out_code, _stream_handle(stream),
+                                       ctypes.byref(t)), "ctp_server_submit")
+        self._pending[t.value] = (x, plan, out_code, tuple(g.sino_shape if fwd else g.vol_shape))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: Optional[float] = None):
+        """Block until the request is done; its output as a view into the arena."""
+        ptr = ctypes.c_void_p()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        _check(lib().ctp_server_wait(self.handle, ticket, us, ctypes.byref(ptr)), "ctp_server_wait")
+        x, plan, out_code, shape = self._pending[ticket]
+        self._pending[ticket] = (None, plan, out_code, shape)   # input no longer needed
+        dt = _torch_dtype(out_code)
+        off = ptr.value - self.arena.data_ptr()
+        n = int(np.prod(shape)) * (4 if out_code == CTP_F32 else 2)
+        return self.arena[off:off + n].view(dt).view(shape)
+
+    def query(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(lib().ctp_server_query(self.handle, ticket, ctypes.byref(done), None),
+               "ctp_server_query")
+        return bool(done.value)
+
+    def info(self, ticket: int) -> dict:
+        i = _RequestInfo()
+        _check(lib().ctp_server_info(self.handle, ticket, ctypes.byref(i)), "ctp_server_info")
+        return {"submit_ns": i.submit_ns, "admit_ns": i.admit_ns, "done_ns": i.done_ns,
+                "batch": i.batch, "slot": i.slot}
+
+    def release(self, ticket: int, stream=None):
+        """Return the request's output to the arena once the work queued so far on ``stream``
+        (default: the current stream) has run."""
+        _check(lib().ctp_server_release(self.handle, ticket, _stream_handle(stream)),
+               "ctp_server_release")
+        self._pending.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().ctp_server_get_stats(self.handle, ctypes.byref(st)), "ctp_server_get_stats")
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            h, self.handle = self.handle, ctypes.c_void_p()
+            _check(lib().ctp_server_destroy(h), "ctp_server_destroy")
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+def _dtype_code_of(dtype) -> int:
+    import torch
+    codes = {torch.float32: CTP_F32, torch.bfloat16: CTP_BF16, torch.float16: CTP_F16}
+    if dtype not in codes:
+        raise TypeError(f"unsupported dtype {dtype}: use float32, bfloat16 or float16")
+    return codes[dtype]

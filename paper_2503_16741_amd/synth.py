@@ -150,6 +150,21 @@ def curved_c3() -> Geometry:
                     sad=595.0, sdd=1085.0)
 
 
+def serving_ladder() -> list:
+    """Geometries a serving stream draws from: a 2D fan beam 256^2 at 0.5 mm with 360 views on
+    a flat 512 x 1 mm detector (SAD 500, SDD 1000), and 3D circular cone beams 128^3, 256^3 and
+    384^3 at 0.4 mm with 400 views on a flat 640 x 480 detector at 0.6 mm (SAD 785, SDD 1200)."""
+    out = [("fan2d_256", Geometry(kind="fan2d", det="flat", nx=256, ny=256, nz=1, dx=0.5,
+                                  dy=0.5, dz=1.0, nu=512, nv=1, du=1.0, dv=1.0, n_views=360,
+                                  theta=full_circle(360), sad=500.0, sdd=1000.0))]
+    for n in (128, 256, 384):
+        out.append((f"cone_{n}", Geometry(kind="cone", det="flat", nx=n, ny=n, nz=n, dx=0.4,
+                                          dy=0.4, dz=0.4, nu=640, nv=480, du=0.6, dv=0.6,
+                                          n_views=400, theta=full_circle(400), sad=785.0,
+                                          sdd=1200.0)))
+    return out
+
+
 def noncirc_c4(seed: int = 0) -> Geometry:
     """3D non-circular cone beam: 384^3 at 0.4 mm, 500 views, flat 640 x 480 at 0.6 mm,
     SAD 785 mm, SDD 1200 mm, with per-view seeded pose jitter: source offsets

@@ -37,10 +37,45 @@ def test_exports_every_declared_function(ct):
         assert hasattr(lib, n), n
 
 
+def test_server_header_exports(ct):
+    text = open(os.path.join(ROOT, "include", "ctserve.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(ctp_[a-z_]+)\s*\(", text)))
+    assert set(names) == set(ct.EXPORTED_SERVER)
+    for n in names:
+        assert hasattr(ct.lib(), n), n
+
+
 def test_status_strings(ct):
     assert ct.ctp_status_string(0) == "ok"
     assert ct.ctp_status_string(-1) == "invalid argument"
     assert ct.ctp_status_string(-2) == "unsupported"
+    assert ct.ctp_status_string(-3) == "out of memory"
+    assert ct.ctp_status_string(-4) == "device error"
+    assert ct.ctp_status_string(-5) == "timed out"
+
+
+def test_server_argument_validation(ct):
+    """Server entry points reject bad arguments before touching a device."""
+    L = ct.lib()
+    out = ctypes.c_void_p()
+    assert L.ctp_server_create(None, ctypes.byref(out)) == -1
+    bad = [(None, 1 << 20, 2, 4), (0x10000, 100, 2, 4), (0x10010, 1 << 20, 2, 4),
+           (0x10000, 1 << 20, 0, 4), (0x10000, 1 << 20, 17, 4), (0x10000, 1 << 20, 2, 0),
+           (0x10000, 1 << 20, 2, 1025)]
+    for arena, nbytes, slots, mb in bad:
+        cfg = ct._ServerConfig(arena, nbytes, slots, mb)
+        assert L.ctp_server_create(ctypes.byref(cfg), ctypes.byref(out)) == -1, (arena, nbytes,
+                                                                                 slots, mb)
+    t = ctypes.c_uint64()
+    assert L.ctp_server_submit(None, None, 0, None, 0, 0, None, ctypes.byref(t)) == -1
+    assert L.ctp_server_wait(None, 1, 0, None) == -1
+    done = ctypes.c_int()
+    assert L.ctp_server_query(None, 1, ctypes.byref(done), None) == -1
+    assert L.ctp_server_info(None, 1, None) == -1
+    assert L.ctp_server_release(None, 1, None) == -1
+    assert L.ctp_server_get_stats(None, None) == -1
+    assert L.ctp_server_destroy(None) == 0
 
 
 def geom(**over):
