@@ -23,6 +23,7 @@ _SOURCES = ("ctoracle.c", "exact_ray.c")
 _lib = None
 
 METHODS = {"sf": 0, "dd": 1}
+MODES = ("proj", "recon")
 KIND = {"fan2d": 0, "cone": 1, "cone_noncirc": 2}
 DET = {"flat": 0, "curved": 1}
 
@@ -98,6 +99,17 @@ def _cgeom(geom):
     return g, keep
 
 
+def _code(method: str, mode: str) -> int:
+    """Oracle method code: 0 = SF, 1 = DD, 2 = SF in "recon" mode (FBP weighting)."""
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {MODES}")
+    if mode == "recon":
+        if method != "sf":
+            raise NotImplementedError("recon mode is defined for the SF projector")
+        return 2
+    return METHODS[method]
+
+
 def _check(rc):
     if rc == -2:
         raise NotImplementedError("geometry/method combination not defined by the oracle")
@@ -105,10 +117,10 @@ def _check(rc):
         raise ValueError(f"oracle error {rc}")
 
 
-def forward(geom, vol, method: str = "sf", views=None) -> np.ndarray:
+def forward(geom, vol, method: str = "sf", views=None, mode: str = "proj") -> np.ndarray:
     """y = A x for the listed views (default: all).  vol: vol_shape (or [B] + vol_shape).
     Returns float64 [len(views)][nv][nu] (2D: [len(views)][nu]), with a leading batch
-    axis when vol has one."""
+    axis when vol has one.  mode "recon": the transpose of the FBP back projection."""
     vol = np.asarray(vol)
     batched = vol.ndim == len(geom.vol_shape) + 1
     vols = vol if batched else vol[None]
@@ -120,16 +132,17 @@ def forward(geom, vol, method: str = "sf", views=None) -> np.ndarray:
     for v in vols:
         v64 = np.ascontiguousarray(v, dtype=np.float64)
         out = np.zeros((views.size, nv, geom.nu), dtype=np.float64)
-        _check(lib().orc_forward(ctypes.byref(g), METHODS[method], _ptr(v64), int(views.size),
+        _check(lib().orc_forward(ctypes.byref(g), _code(method, mode), _ptr(v64), int(views.size),
                                  _ptr(views), _ptr(out)))
         outs.append(out.reshape((views.size, geom.nu)) if geom.kind == "fan2d" else out)
     del keep
     return np.stack(outs) if batched else outs[0]
 
 
-def adjoint(geom, sino, method: str = "sf", voxels=None) -> np.ndarray:
+def adjoint(geom, sino, method: str = "sf", voxels=None, mode: str = "proj") -> np.ndarray:
     """x = A^T y.  sino: sino_shape (or [B] + sino_shape).  With voxels=None returns the full
-    volume (vol_shape); otherwise the values at the given linear voxel indices."""
+    volume (vol_shape); otherwise the values at the given linear voxel indices.  mode "recon":
+    the FBP back projection sum_b (SAD/W)^2 (normalised SF footprint) y_b."""
     sino = np.asarray(sino)
     batched = sino.ndim == len(geom.sino_shape) + 1
     sinos = sino if batched else sino[None]
@@ -141,7 +154,7 @@ def adjoint(geom, sino, method: str = "sf", voxels=None) -> np.ndarray:
     for s in sinos:
         s64 = np.ascontiguousarray(s, dtype=np.float64)
         out = np.zeros(idx.size, dtype=np.float64)
-        _check(lib().orc_adjoint(ctypes.byref(g), METHODS[method], _ptr(s64), int(idx.size),
+        _check(lib().orc_adjoint(ctypes.byref(g), _code(method, mode), _ptr(s64), int(idx.size),
                                  _ptr(idx), _ptr(out)))
         outs.append(out.reshape(geom.vol_shape) if full else out)
     del keep
@@ -179,3 +192,10 @@ def ray_integrals(vol, shape_xyz, pitch_xyz, origin_xyz, a, b) -> np.ndarray:
     lib().exr_integrals(_ptr(v64), _ptr(n), _ptr(h), _ptr(o), int(a.shape[0]), _ptr(a),
                         _ptr(b), _ptr(out))
     return out
+
+
+def fbp(geom, sino, window: str = "ram-lak", voxels=None) -> np.ndarray:
+    """Filtered back projection (fan beam) / FDK (cone beam) of a circular scan: the ramp
+    filter of ``ramp.py`` followed by the "recon"-mode back projection."""
+    from .ramp import ramp_filter
+    return adjoint(geom, ramp_filter(geom, sino, window), voxels=voxels, mode="recon")

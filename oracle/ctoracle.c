@@ -19,6 +19,9 @@
  *   DD:  per view a driving axis; detector cell edges mapped onto each voxel plane through
  *        the source; weight = fractional overlap in the plane x fractional overlap along z
  *        (rows mapped along the column-centre ray) x the ray's path through the slab.
+ * "recon" mode (Section 2.3: the FBP back projection carries a depth-dependent weight) uses
+ * the SF footprint normalised to unit sum as the interpolation kernel and weights each view by
+ * (SAD / W)^2; its forward projection is the transpose (method code 2, circular scans).
  * Every point the paper leaves open is fixed by one reading; the readings are listed with
  * the design notes.  Everything is double precision, no fast-math, no reordering beyond
  * skipping cells that the footprint does not reach.
@@ -26,7 +29,8 @@
  * Parity status: SF and DD forward/adjoint are pinned by the test suite (closed form of a
  * single voxel, parallel-beam exactness against exact path lengths, mass conservation,
  * adjoint identity, symmetries, reductions, brute-force ray integration, analytic
- * ellipsoids, empty/outside-FOV cases).
+ * ellipsoids, empty/outside-FOV cases); recon mode by the closed-form sum of its weights,
+ * the adjoint identity and filtered back projection of analytic discs and balls.
  */
 #include <math.h>
 #include <stdint.h>
@@ -223,6 +227,10 @@ typedef struct {
     double amp;           /* l_phi0 */
     double *F1;           /* [ni] cell-averaged transaxial trapezoid */
     double *F2;           /* [nj] cell-averaged axial trapezoid (3D) */
+    double Au, Av;        /* areas of the unit-height trapezoids in cells (sum of F1 / F2 over an
+                             unbounded detector); Av = 1 in 2D */
+    double W;             /* depth of the voxel centre: flat (s - c).n, curved the in-plane
+                             distance from the source */
 } sf_fp;
 
 /*
@@ -276,6 +284,7 @@ static int sf_footprint(const orc_geom *g, const orc_frame *f, int ix, int iy, i
         kap[2] = tmin;
         kap[3] = tmax;
         sort4(kap);
+        fp->Av = 0.5 * (kap[3] + kap[2] - kap[1] - kap[0]) / g->dv;
         const double ve0 = f->v_first - 0.5 * g->dv;
         if (!cell_range(kap[0], kap[3], ve0, g->dv, g->nv, &fp->j0, &fp->nj))
             return 0;
@@ -288,6 +297,19 @@ static int sf_footprint(const orc_geom *g, const orc_frame *f, int ix, int iy, i
         fp->j0 = 0;
         fp->nj = 1;
         fp->F2[0] = 1.0;
+        fp->Av = 1.0;
+    }
+    fp->Au = 0.5 * (tau[3] + tau[2] - tau[1] - tau[0]) / g->du;
+    {
+        const double w = (f->s[0] - c[0]) * f->n[0] + (f->s[1] - c[1]) * f->n[1] +
+                         (f->s[2] - c[2]) * f->n[2];
+        if (g->det == 1) {
+            const double a = (c[0] - f->s[0]) * f->eu[0] + (c[1] - f->s[1]) * f->eu[1] +
+                             (c[2] - f->s[2]) * f->eu[2];
+            fp->W = sqrt(a * a + w * w);
+        } else {
+            fp->W = w;
+        }
     }
 
     for (int i = 0; i < fp->ni; ++i) {
@@ -313,6 +335,20 @@ static double sf_cell_amp(const orc_geom *g, const orc_frame *f, int i, int j)
     det_point(g, f, f->u_first + i * g->du, f->v_first + j * g->dv, q);
     const double rx = q[0] - f->s[0], ry = q[1] - f->s[1], rz = q[2] - f->s[2];
     return sqrt(rx * rx + ry * ry + rz * rz) / hypot(rx, ry);
+}
+
+/*
+ * "recon" mode (Section 2.3: the back projection of FBP carries a depth-dependent weight).
+ * The voxel's SF footprint serves as an interpolation kernel normalised to unit sum,
+ * F1_i F2_j / (Au Av), and each view is weighted by (SAD / W)^2 with W the voxel centre's
+ * depth (flat: distance along the detector normal; curved: in-plane distance from the source),
+ * the 1/U^2 factor of fan-beam and cone-beam FBP.  No per-cell amplitude.  The forward
+ * projection in this mode is the transpose of that back projection.
+ */
+static double sf_recon_weight(const orc_geom *g, int b, const sf_fp *fp)
+{
+    const double r = g->sad[b] / fp->W;
+    return r * r / (fp->Au * fp->Av);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -443,8 +479,10 @@ static double dd_cell_amp(const orc_geom *g, const orc_frame *f, int i, int j)
 
 static int check_geom(const orc_geom *g, int method)
 {
-    if (g->kind < 0 || g->kind > 2 || g->det < 0 || g->det > 1)
+    if (g->kind < 0 || g->kind > 2 || g->det < 0 || g->det > 1 || method < 0 || method > 2)
         return -1;
+    if (method == 2 && g->kind == 2)
+        return -2;          /* recon mode: circular scans (FBP / FDK) */
     if (g->kind == 2 && g->det == 1)
         return -2;          /* non-circular geometries use flat detectors only */
     if (method == 1 && g->kind == 2)
@@ -464,7 +502,8 @@ static int nv_of(const orc_geom *g) { return g->kind == 0 ? 1 : g->nv; }
 
 /* Forward projection of one volume for the listed views.
  * vol:  [nz][ny][nx] (nz = 1 in 2D);  sino: [n_list][nv][nu] (nv = 1 in 2D), overwritten.
- * method: 0 = SF, 1 = DD.  Returns 0 on success, <0 on an unsupported/invalid geometry. */
+ * method: 0 = SF, 1 = DD, 2 = SF in "recon" mode (the transpose of the FBP back projection,
+ * see sf_recon_weight).  Returns 0 on success, <0 on an unsupported/invalid geometry. */
 int orc_forward(const orc_geom *g, int method, const double *vol, int n_list, const int32_t *views,
                 double *sino)
 {
@@ -492,13 +531,14 @@ int orc_forward(const orc_geom *g, int method, const double *vol, int n_list, co
                         const double x = vol[vol_index(g, ix, iy, iz)];
                         if (x == 0.0)
                             continue;
-                        if (method == 0) {
-                            sf_fp fp = {0, 0, 0, 0, 0.0, F1, F2};
+                        if (method != 1) {
+                            sf_fp fp = {0, 0, 0, 0, 0.0, F1, F2, 0.0, 0.0, 0.0};
                             if (!sf_footprint(g, &f, ix, iy, iz, &fp))
                                 continue;
+                            const double amp = method == 2 ? sf_recon_weight(g, views[vi], &fp) : fp.amp;
                             for (int j = 0; j < fp.nj; ++j)
                                 for (int i = 0; i < fp.ni; ++i)
-                                    y[(int64_t)(fp.j0 + j) * nu + fp.i0 + i] += x * fp.amp * fp.F1[i] * fp.F2[j];
+                                    y[(int64_t)(fp.j0 + j) * nu + fp.i0 + i] += x * amp * fp.F1[i] * fp.F2[j];
                         } else {
                             dd_fp fp = {0, 0, F1, j0, nj, Fz};
                             if (!dd_footprint(g, &f, ix, iy, iz, &fp))
@@ -510,7 +550,8 @@ int orc_forward(const orc_geom *g, int method, const double *vol, int n_list, co
                     }
             for (int j = 0; j < nv; ++j)
                 for (int i = 0; i < nu; ++i)
-                    y[(int64_t)j * nu + i] *= method == 0 ? sf_cell_amp(g, &f, i, j) : dd_cell_amp(g, &f, i, j);
+                    y[(int64_t)j * nu + i] *= method == 0 ? sf_cell_amp(g, &f, i, j)
+                                              : method == 1 ? dd_cell_amp(g, &f, i, j) : 1.0;
         }
         free(F1);
         free(F2);
@@ -549,7 +590,8 @@ int orc_adjoint(const orc_geom *g, int method, const double *sino, int64_t n_lis
         for (int j = 0; j < nv; ++j)
             for (int i = 0; i < nu; ++i) {
                 const int64_t k = b * view_sz + (int64_t)j * nu + i;
-                ys[k] = sino[k] * (method == 0 ? sf_cell_amp(g, &fr[b], i, j) : dd_cell_amp(g, &fr[b], i, j));
+                ys[k] = sino[k] * (method == 0 ? sf_cell_amp(g, &fr[b], i, j)
+                                   : method == 1 ? dd_cell_amp(g, &fr[b], i, j) : 1.0);
             }
 
 #pragma omp parallel
@@ -567,13 +609,14 @@ int orc_adjoint(const orc_geom *g, int method, const double *sino, int64_t n_lis
             double acc = 0.0;
             for (int b = 0; b < g->n_views; ++b) {
                 const double *y = ys + b * view_sz;
-                if (method == 0) {
-                    sf_fp fp = {0, 0, 0, 0, 0.0, F1, F2};
+                if (method != 1) {
+                    sf_fp fp = {0, 0, 0, 0, 0.0, F1, F2, 0.0, 0.0, 0.0};
                     if (!sf_footprint(g, &fr[b], ix, iy, iz, &fp))
                         continue;
+                    const double amp = method == 2 ? sf_recon_weight(g, b, &fp) : fp.amp;
                     for (int j = 0; j < fp.nj; ++j)
                         for (int i = 0; i < fp.ni; ++i)
-                            acc += fp.amp * fp.F1[i] * fp.F2[j] * y[(int64_t)(fp.j0 + j) * nu + fp.i0 + i];
+                            acc += amp * fp.F1[i] * fp.F2[j] * y[(int64_t)(fp.j0 + j) * nu + fp.i0 + i];
                 } else {
                     dd_fp fp = {0, 0, F1, j0, nj, Fz};
                     if (!dd_footprint(g, &fr[b], ix, iy, iz, &fp))
@@ -618,8 +661,8 @@ int orc_count(const orc_geom *g, int method, int n_list, const int32_t *views, i
                 make_frame(g, views[vi], &f);
                 for (int iy = 0; iy < g->ny; ++iy)
                     for (int ix = 0; ix < g->nx; ++ix) {
-                        if (method == 0) {
-                            sf_fp fp = {0, 0, 0, 0, 0.0, F1, F2};
+                        if (method != 1) {
+                            sf_fp fp = {0, 0, 0, 0, 0.0, F1, F2, 0.0, 0.0, 0.0};
                             if (!sf_footprint(g, &f, ix, iy, iz, &fp))
                                 continue;
                             vv += 1;
