@@ -270,6 +270,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dd", action="store_true")
+    ap.add_argument("--no-recon", action="store_true")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB device copy, one SF forward and one SF back projection "
@@ -394,6 +395,31 @@ def main():
                      "back_ms": round(float(bwd_d.mean()), 4),
                      "p99_ms": round(float(np.percentile(pair_d, 99)), 4)}
         plan_dd.close()
+
+    if not args.no_recon:
+        # FDK of the same scan: ramp filter + recon-mode (depth-weighted) back projection
+        plan_r = ctproj.ctp_plan_create(g, "sf", "recon")
+        q = torch.empty_like(sino)
+        ctproj.ctp_ramp_filter(plan_r, sino, q)
+        ctproj.ctp_backproject(plan_r, q, back)
+        torch.cuda.synchronize()
+        rsteps = max(3, args.steps // 4)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(rsteps)]
+        for k in range(rsteps):
+            ev[k][0].record(stream)
+            ctproj.ctp_ramp_filter(plan_r, sino, q)
+            ev[k][1].record(stream)
+            ctproj.ctp_backproject(plan_r, q, back)
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        ramp = np.array([e[0].elapsed_time(e[1]) for e in ev])
+        bpr = np.array([e[1].elapsed_time(e[2]) for e in ev])
+        out["fdk"] = {"ramp_ms": round(float(ramp.mean()), 4),
+                      "backproject_ms": round(float(bpr.mean()), 4),
+                      "gups": round(vv / ((ramp.mean() + bpr.mean()) * 1e-3) / 1e9, 3)}
+        print(f"[bench] FDK: ramp {ramp.mean():.3f} ms, recon back projection {bpr.mean():.3f} ms",
+              file=sys.stderr, flush=True)
+        plan_r.close()
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

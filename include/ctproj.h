@@ -58,6 +58,16 @@ typedef enum { CTP_SF = 0, CTP_DD = 1 } ctp_method;
 typedef enum { CTP_F32 = 0, CTP_BF16 = 1, CTP_F16 = 2 } ctp_dtype;
 /* Direction of a call, for workspace queries. */
 typedef enum { CTP_FORWARD = 0, CTP_BACKWARD = 1 } ctp_direction;
+/* Projection modes (Section 2.3).  PROJ: the standard projector pair.  RECON: the back
+ * projection of filtered back projection, with a depth-dependent weight per view: the SF
+ * footprint of each voxel is used as an interpolation kernel normalised to unit sum and view
+ * b is weighted by (SAD_b / W_b)^2, W_b the depth of the voxel centre (flat detector: distance
+ * from the source along the detector normal; curved: in-plane distance from the source).  The
+ * forward projection in RECON mode is the exact transpose of that back projection.  RECON is
+ * built for SF on circular scans (2D fan, 3D circular cone; flat or curved). */
+typedef enum { CTP_MODE_PROJ = 0, CTP_MODE_RECON = 1 } ctp_mode;
+/* Ramp filter windows (ctp_ramp_filter). */
+typedef enum { CTP_WINDOW_RAMLAK = 0, CTP_WINDOW_SHEPP_LOGAN = 1 } ctp_window;
 
 /*
  * Geometry descriptor (Section 2.2, Table 1).  Each per-view parameter is a host pointer to
@@ -86,16 +96,20 @@ typedef struct ctp_plan ctp_plan;   /* opaque; immutable after creation */
 /*
  * Expand the geometry per view in FP64 on the host (source, detector frame, projection
  * constants, DD driving axis), validate it, and upload the per-view table to the current
- * HIP device.  The plan is bound to that device.
- * Errors: CTP_EINVAL for non-positive sizes or spacings, a len field other than 0, 1 or
- * n_views, a NULL pointer with a non-zero len, any corner of the volume at or behind the
- * source plane in some view, or (DD) a detector column ray parallel to the driving planes;
- * CTP_EUNSUPPORTED for a curved detector with a non-circular scan (Section 2.3), a curved
- * detector with a non-zero x_src, DD with a non-circular scan, or a footprint wider than 16
- * detector columns; CTP_ENOMEM / CTP_EDEVICE for allocation / upload failures.
+ * HIP device.  The plan is bound to that device.  The paper's Projector(geom, mode, method,
+ * direction) maps to a plan of (geometry, method, mode) and the choice of ctp_project /
+ * ctp_backproject.
+ * Errors: CTP_EINVAL for an unknown method or mode, non-positive sizes or spacings, a len
+ * field other than 0, 1 or n_views, a NULL pointer with a non-zero len, any corner of the
+ * volume at or behind the source plane in some view, or (DD) a detector column ray parallel
+ * to the driving planes; CTP_EUNSUPPORTED for a curved detector with a non-circular scan
+ * (Section 2.3), a curved detector with a non-zero x_src, DD with a non-circular scan, RECON
+ * mode other than SF on a circular scan, or a footprint wider than 16 detector columns;
+ * CTP_ENOMEM / CTP_EDEVICE for allocation / upload failures.
  * On success *out owns a device table of 128 bytes per view.
  */
-ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_plan **out);
+ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_mode mode,
+                           ctp_plan **out);
 
 /* Free the plan's device table.  The caller must ensure no call using it is in flight.
  * NULL is accepted. */
@@ -144,6 +158,27 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
 ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype,
                            void *vol, ctp_dtype vol_dtype, int64_t batch, int accumulate,
                            void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Discrete ramp filter of filtered back projection (Section 2.1; fan-beam and FDK weighting of
+ * a full circular scan with uniformly spaced views, dbeta = 2 pi / n_views), applied to every
+ * detector row of `batch` sinograms of the plan's geometry (any method or mode):
+ *   flat:   q_i = dbeta (M du / 2) sum_k h_du(i - k) c_k p_k,   M = SDD / SAD,
+ *           c_k = SDD / sqrt(SDD^2 + (u_k - x_src)^2 + (v_j - z_src)^2)   (2D: no v term);
+ *   curved: q_i = dbeta (dg / (2 SAD)) sum_k (g_ik / sin g_ik)^2 h_dg(i - k) c_k p_k,
+ *           dg = du / SDD, g_ik = (i - k) dg,  c_k = cos(u_k / SDD) SDD / sqrt(SDD^2 + (v_j - z_src)^2);
+ * with h_a the band-limited ramp sampled at pitch a: Ram-Lak h(0) = 1/(4a^2), h(n) = 0 for even
+ * n, -1/(n pi a)^2 for odd n; Shepp-Logan h(n) = -2 / (pi^2 a^2 (4n^2 - 1)).  The back
+ * projection of q by a RECON-mode plan is the FBP (2D) / FDK (3D) reconstruction.
+ * sino / out: device pointers in the sinogram layout; out may equal sino when the storage types
+ * agree (rows are filtered in place).  FP32 arithmetic.  Asynchronous on `stream`.
+ * Errors: CTP_EINVAL (NULL pointers, batch < 1, unknown dtype or window, partial overlap or
+ * in-place with different types, plan of another device), CTP_EUNSUPPORTED (non-circular scan,
+ * more than 5120 detector columns or 65535 views), CTP_EDEVICE (launch).
+ */
+ctp_status ctp_ramp_filter(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *out,
+                           ctp_dtype out_dtype, int64_t batch, ctp_window window,
+                           hipStream_t stream);
 
 /* Static description of a status code. */
 const char *ctp_status_string(ctp_status status);

@@ -68,19 +68,21 @@ class BackprojectFn(torch.autograd.Function):
 
 
 class Projector(torch.nn.Module):
-    """Projector(geom, mode, method, direction) with mode 'proj' (standard projection),
-    method 'SF' or 'DD', direction 'forward' (A) or 'backward' (A^T)."""
+    """Projector(geom, mode, method, direction) with mode 'proj' (standard projection) or
+    'recon' (the depth-weighted back projection of FBP and its transpose; SF on circular
+    scans), method 'SF' or 'DD', direction 'forward' (A) or 'backward' (A^T)."""
 
     def __init__(self, geom: Geometry, mode: str = "proj", method: str = "SF",
                  direction: str = "forward"):
         super().__init__()
-        if mode != "proj":
-            raise NotImplementedError("only 'proj' mode is built; 'recon' (FBP weighting) is not")
+        if mode not in ("proj", "recon"):
+            raise ValueError("mode must be 'proj' or 'recon'")
         if method.upper() not in ("SF", "DD"):
             raise NotImplementedError(f"projector method {method!r} is not built (SF, DD are)")
         if direction not in ("forward", "backward"):
             raise ValueError("direction must be 'forward' or 'backward'")
         self.geom = geom
+        self.mode = mode
         self.method = method.lower()
         self.direction = direction
         self._plan = None
@@ -88,7 +90,7 @@ class Projector(torch.nn.Module):
     @property
     def plan(self):
         if self._plan is None:
-            self._plan = ctproj.ctp_plan_create(self.geom, self.method)
+            self._plan = ctproj.ctp_plan_create(self.geom, self.method, self.mode)
         return self._plan
 
     def forward(self, t: torch.Tensor) -> torch.Tensor:

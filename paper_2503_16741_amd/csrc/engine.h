@@ -20,7 +20,9 @@ int plan_device(const ctp_plan *plan);
 
 enum Geom : int { kFan2D = 0, kCirc = 1, kNonCirc = 2 };
 enum Det : int { kFlat = 0, kCurved = 1 };
-enum Method : int { kSF = 0, kDD = 1 };
+// kSFR: the SF footprint in "recon" mode (normalised to unit sum, weighted by (SAD/W)^2; the
+// back projection of FBP / FDK and its transpose).
+enum Method : int { kSF = 0, kDD = 1, kSFR = 2 };
 
 constexpr int kStripW = 16;      // detector columns owned by one forward work-group
 constexpr int kMaxCells = 16;    // widest supported transaxial footprint (columns)
@@ -52,7 +54,8 @@ struct alignas(16) ViewRec {
     float sd_ev;    // (s-d).ev (mm)
     int ydrv;       // DD: 1 = planes y = const, 0 = planes x = const
     float ddC;      // DD axial constant: -((d-s).z + ve0)/dv (row units)
-    float pad[4];
+    float sad;      // nominal source-to-axis distance (mm): FBP weights and ramp-filter scale
+    float pad[3];
 };
 static_assert(sizeof(ViewRec) == 128, "ViewRec must stay 128 bytes");
 
@@ -104,5 +107,11 @@ hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *vi
 hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,
                            const float *ysc, float *vol, int64_t batch, int accumulate,
                            hipStream_t st);
+// Cosine-weighted ramp filter of every detector row (circular scans).  window: 0 = Ram-Lak,
+// 1 = Shepp-Logan; dbeta: angular step of the scan; in / out storage types as above (in and
+// out may be the same buffer when their types agree).
+hipError_t launch_ramp(const Params &p, const LaunchCfg &c, const ViewRec *views, const void *in,
+                       int in_dtype, void *out, int out_dtype, int64_t batch, int window,
+                       float dbeta, hipStream_t st);
 
 }  // namespace ctp

@@ -30,7 +30,7 @@
 #define CTP_FWD_FAST 1
 #endif
 #ifndef CTP_CVT_TRUNC
-#define CTP_CVT_TRUNC 1
+#define CTP_CVT_TRUNC 0
 #endif
 #ifndef CTP_BWD_FAST
 #define CTP_BWD_FAST 1
@@ -52,15 +52,19 @@ template <> __device__ __forceinline__ __hip_bfloat16 from_f32<__hip_bfloat16>(f
 }
 template <> __device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half(v); }
 
-// FP32 -> fixed point for the forward accumulators.  Truncation toward zero (one
-// instruction) biases each term by at most one unit of 2^-S; with the scale set so the
-// largest possible cell sum is 2^30 units, a thousand terms move a cell by ~1e-6 of that.
+// FP32 -> fixed point for the forward accumulators: round to nearest (ties upward),
+// floor(x + 0.5), in one instruction (v_cvt_rpi_i32_f32; the compiler's round-to-nearest-even
+// path takes two).  Unbiased, so a cell's error grows like the square root of its number of
+// terms, each at most half a unit of 2^-S.  In-range inputs only (the per-item scale keeps
+// every partial sum below 2^30).
 __device__ __forceinline__ int to_fixed(float x)
 {
 #if CTP_CVT_TRUNC
     return (int)x;
 #else
-    return __float2int_rn(x);
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
 #endif
 }
 
@@ -201,6 +205,30 @@ __device__ __forceinline__ void sf_cell_weights(const SFCol &c, int cs, int nc, 
     }
 }
 
+// Recon mode (circular scans): amplitude (SAD / W)^2 / A_u of a voxel column, W the depth of
+// the column centre (flat: along the detector normal; curved: in-plane distance from the
+// source) and A_u the area of its unit-height transaxial trapezoid in columns, so that the
+// column weights sum to (SAD / W)^2 on an unbounded detector.
+template <int DET>
+__device__ __forceinline__ float sf_recon_col_amp(const ViewRec &V, const SFCol &c, float xc,
+                                                  float yc)
+{
+    const float Wc = V.sn - fmaf(xc, V.n[0], yc * V.n[1]);
+    float W = Wc;
+    if (DET == kCurved) {
+        const float ac = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], -V.seu));
+        W = sqrtf(fmaf(ac, ac, Wc * Wc));
+    }
+    const float r = fdiv(V.sad, W);
+    return fdiv(r * r, 0.5f * ((c.t3 + c.t2) - (c.t1 + c.t0)));
+}
+
+// Area of an axial trapezoid in rows (exact corners; recon-mode normalisation).
+__device__ __forceinline__ float trap_area(const Trap &t)
+{
+    return 0.5f * ((t.k3 + t.k2) - (t.k1 + t.k0));
+}
+
 // DD: columns touched by the voxel's in-plane interval on its driving plane, the fraction of
 // each mapped column covered, and the axial map scale (rows per mm) along each column's
 // centre ray.
@@ -275,7 +303,7 @@ __device__ __forceinline__ void dd_cell_weights(const ViewRec &V, const Params &
 template <int GEOM, int DET, int METHOD>
 __device__ __forceinline__ float cell_amp(const ViewRec &V, const Params &P, int i, int j)
 {
-    if (GEOM == kFan2D && METHOD == kSF)
+    if (METHOD == kSFR || (GEOM == kFan2D && METHOD == kSF))
         return 1.0f;
     const float u = fmaf((float)i + 0.5f, P.du, V.ue0);
     const float v = GEOM == kFan2D ? 0.0f : fmaf((float)j + 0.5f, P.dv, V.ve0);
@@ -463,7 +491,7 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
            af - an - bn <= -m && fmaf(bf - bn, zl, af - an - bn) <= -m;
 }
 
-template <int K>
+template <int K, bool NORM>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
                                            const float (&w)[K], int nc, int *accs, int SW,
@@ -495,6 +523,13 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
         // skip runs entirely outside the row window
         if (qf[nq] < 0.0f || p[0] >= fR)
             continue;
+        if constexpr (NORM) {
+            // recon mode: each voxel's axial trapezoid normalised to unit area
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < nq)
+                    v[q] *= fdiv(2.0f, (p[q + 1] + qf[q + 1]) - (p[q] + qf[q]));
+        }
         int tp = max((int)floorf(p[0]), -1);     // last edge handled (C = 0 at floor(p0))
         uint32_t Cprev = 0u, S = 0u;
         float vm1 = 0.0f;
@@ -719,9 +754,11 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
             const bool valid = ix < P.nx && iy < P.ny;
             const float xc = fmaf((float)ix, P.dx, P.x0), yc = fmaf((float)iy, P.dy, P.y0);
 
-            if constexpr (METHOD == kSF && GEOM != kNonCirc) {
+            if constexpr (METHOD != kDD && GEOM != kNonCirc) {
                 SFCol col;
                 sf_column<DET>(V, P, xc, yc, 0.0f, col);
+                if constexpr (METHOD == kSFR)
+                    col.amp = sf_recon_col_amp<DET>(V, col, xc, yc);
                 const int cmin = col.o + (int)floorf(col.t0), cmax = col.o + (int)floorf(col.t3);
                 const int cs = max(cmin, i_lo), ce = min(cmax, i_hi - 1);
                 const int nc = valid ? max(ce - cs + 1, 0) : 0;
@@ -745,8 +782,8 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
                         if (sf_fast_ok(s_an, s_bn, s_af, s_bf, P.nz)) {
-                            sf_fwd_run<K>(colp, P.nz, s_an, s_bn, s_af, s_bf, sw, s_nc, accs,
-                                          SW, R, lane);
+                            sf_fwd_run<K, METHOD == kSFR>(colp, P.nz, s_an, s_bn, s_af, s_bf, sw,
+                                                          s_nc, accs, SW, R, lane);
                             continue;
                         }
                     }
@@ -772,8 +809,9 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                                         atomicAdd(a + k, to_fixed(val * sw[k]));
                             } else {
                                 const Trap tr = sf_axial(s_an, s_bn, s_af, s_bf, (float)z, P.eps);
+                                const float vn = METHOD == kSFR ? fdiv(val, trap_area(tr)) : val;
                                 for_rows(tr, R, [&](int j, float F) {
-                                    const float f = F * val;
+                                    const float f = F * vn;
                                     int *a = accs + j * SW;
 #pragma unroll
                                     for (int k = 0; k < K; ++k)
@@ -932,7 +970,7 @@ __device__ __forceinline__ bool sf_bwd_fast_ok(float an, float bn, float af, flo
     return disjoint && narrow;
 }
 
-template <int K, int NQ>
+template <int K, int NQ, bool NORM>
 __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_t row_stride,
                                             int cs, int nu, int rows, const float (&w)[K],
                                             float an, float bn, float af, float bf, int zc0,
@@ -956,6 +994,7 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
     const float zs = (float)zc0;
     int jc = (int)floorf(fminf(fmaxf(fminf(fmaf(bn, zs, an), fmaf(bf, zs, af)), -1.0f), fr));
     float rc = load_row(jc), rn = load_row(jc + 1), rp = 0.0f, RP = 0.0f, Dprev = 0.0f;
+    float mprev = 0.0f;                               // p + q of the previous face (NORM)
 #pragma unroll
     for (int f = 0; f <= NQ; ++f) {
         if (f <= nq) {
@@ -978,9 +1017,14 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
                 J = a > 0.0f ? fmaf(rp - rc, a * a * h, rc * 0.5f * w) : rc * 0.5f * w;
             }
             const float D = R - J;
-            if (f > 0)
-                acc[f - 1] += D - Dprev;
+            if (f > 0) {
+                if constexpr (NORM)   // recon mode: divide by the slice's trapezoid area
+                    acc[f - 1] += (D - Dprev) * fdiv(2.0f, (p + q) - mprev);
+                else
+                    acc[f - 1] += D - Dprev;
+            }
             Dprev = D;
+            mprev = p + q;
         }
     }
 }
@@ -1027,9 +1071,11 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
             const float *yv = ysb + (int64_t)view * P.sino_view_stride;
             const float zb0 = P.z0 - hz - V.s[2];
 
-            if constexpr (METHOD == kSF && GEOM != kNonCirc) {
+            if constexpr (METHOD != kDD && GEOM != kNonCirc) {
                 SFCol col;
                 sf_column<DET>(V, P, xc, yc, 0.0f, col);
+                if constexpr (METHOD == kSFR)
+                    col.amp = sf_recon_col_amp<DET>(V, col, xc, yc);
                 const int cmin = col.o + (int)floorf(col.t0), cmax = col.o + (int)floorf(col.t3);
                 const int cs = max(cmin, 0), ce = min(cmax, P.nu - 1);
                 const int nc = ce - cs + 1;
@@ -1057,8 +1103,9 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                     const float af = fmaf(col.Af, zb0, V.cv), bf = col.Af * P.dz;
                     const int nq = min(kZChunk, nzv - zc0);
                     if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + nq - 1)) {
-                        sf_bwd_fast<K, kZChunk>(yv, P.sino_row_stride, cs, P.nu, rows_total, w,
-                                                an, bn, af, bf, zc0, nq, acc);
+                        sf_bwd_fast<K, kZChunk, METHOD == kSFR>(yv, P.sino_row_stride, cs, P.nu,
+                                                                rows_total, w, an, bn, af, bf,
+                                                                zc0, nq, acc);
                         continue;
                     }
 #pragma unroll
@@ -1076,6 +1123,8 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                                         rs = fmaf(w[k], yr[k], rs);
                                 s = fmaf(F, rs, s);
                             });
+                            if constexpr (METHOD == kSFR)
+                                s = fdiv(s, trap_area(tr));
                             acc[q] += s;
                         }
                     }
@@ -1341,7 +1390,8 @@ hipError_t amp_launch(const Params &p, const ViewRec *views, const void *in, int
 }
 
 // Expand (geom, det, method, K) into a template instance.  Combinations that the plan rejects
-// (non-circular + curved, non-circular + DD) are never instantiated.
+// (non-circular + curved, non-circular + DD, recon mode off circular SF) are never
+// instantiated.
 template <template <int, int, int, int> class F, typename... A>
 hipError_t dispatch(const LaunchCfg &c, A &&...a);
 
@@ -1365,6 +1415,10 @@ hipError_t dispatch(const LaunchCfg &c, A &&...a)
     if (c.geom == kCirc && c.det == kFlat && c.method == kDD) { CTP_FOR_K(kCirc, kFlat, kDD) }
     if (c.geom == kCirc && c.det == kCurved && c.method == kDD) { CTP_FOR_K(kCirc, kCurved, kDD) }
     if (c.geom == kNonCirc && c.det == kFlat && c.method == kSF) { CTP_FOR_K(kNonCirc, kFlat, kSF) }
+    if (c.geom == kFan2D && c.det == kFlat && c.method == kSFR) { CTP_FOR_K(kFan2D, kFlat, kSFR) }
+    if (c.geom == kFan2D && c.det == kCurved && c.method == kSFR) { CTP_FOR_K(kFan2D, kCurved, kSFR) }
+    if (c.geom == kCirc && c.det == kFlat && c.method == kSFR) { CTP_FOR_K(kCirc, kFlat, kSFR) }
+    if (c.geom == kCirc && c.det == kCurved && c.method == kSFR) { CTP_FOR_K(kCirc, kCurved, kSFR) }
     return hipErrorInvalidValue;
 }
 #undef CTP_FOR_K
@@ -1397,6 +1451,109 @@ struct AmpOp {
         return amp_launch<G, D, M>(p, views, in, dtype, out, batch, st);
     }
 };
+
+// ============================================================================================
+// Ramp filter of filtered back projection: one detector row per work-group.  The row, weighted
+// by the cosine of its rays, and the scaled ramp taps h(n), n = -(nu-1) .. nu-1, sit in LDS;
+// output i is sum_k h(i - k) row[k] (lanes read consecutive taps and the same row element).
+// ============================================================================================
+constexpr int kRampThreads = 256;
+
+template <int DET, typename TI, typename TO>
+__global__ __launch_bounds__(kRampThreads) void ramp_kernel(Params P, const ViewRec *__restrict__ views,
+                                                            const TI *in, TO *out, int window,
+                                                            float dbeta, int two_d)
+{
+    extern __shared__ float sm[];
+    const int nu = P.nu;
+    float *taps = sm;
+    float *row = sm + 2 * nu - 1;
+    const int j = blockIdx.x;            // detector row (3D) or batch item (2D)
+    const int view = blockIdx.y;
+    const int b = blockIdx.z;            // batch item (3D)
+    const ViewRec &V = views[view];
+    const int64_t base = (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
+                         (int64_t)j * P.sino_row_stride;
+    const float sdd = V.sdd, sad = V.sad;
+    const float a = DET == kFlat ? P.du : P.du / sdd;          // pitch of the ramp samples
+    const float scale = DET == kFlat ? dbeta * (sdd / sad) * P.du * 0.5f : dbeta * a / (2.0f * sad);
+    const float c0 = 1.0f / (9.8696044010893586f * a * a);    // 1 / (pi a)^2
+    for (int t = threadIdx.x; t < 2 * nu - 1; t += blockDim.x) {
+        const int n = t - (nu - 1);
+        const float fn = (float)n;
+        float h;
+        if (window == 0)
+            h = n == 0 ? 0.25f / (a * a) : ((n & 1) ? -c0 / (fn * fn) : 0.0f);
+        else
+            h = -2.0f * c0 / (4.0f * fn * fn - 1.0f);
+        if (DET == kCurved && n != 0) {
+            const float g = fn * a, r = g / sinf(g);
+            h *= r * r;
+        }
+        taps[t] = h * scale;
+    }
+    // (s - d).eu: column position of the source's foot on a flat detector
+    const float us = -(V.dms[0] * V.eu[0] + V.dms[1] * V.eu[1] + V.dms[2] * V.eu[2]);
+    const float vz = two_d ? 0.0f : fmaf((float)j + 0.5f, P.dv, V.ve0) - V.sd_ev;
+    for (int k = threadIdx.x; k < nu; k += blockDim.x) {
+        const float u = fmaf((float)k + 0.5f, P.du, V.ue0);
+        float c;
+        if (DET == kFlat) {
+            const float du_ = u - us;
+            c = sdd / sqrtf(fmaf(sdd, sdd, fmaf(du_, du_, vz * vz)));
+        } else {
+            c = cosf(u / sdd) * sdd / sqrtf(fmaf(sdd, sdd, vz * vz));
+        }
+        row[k] = to_f32(in[base + k]) * c;
+    }
+    __syncthreads();                     // the whole row is read before any output is written
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
+        const float *h = taps + (i + nu - 1);
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+        int k = 0;
+        for (; k + 3 < nu; k += 4) {
+            s0 = fmaf(h[-k], row[k], s0);
+            s1 = fmaf(h[-k - 1], row[k + 1], s1);
+            s2 = fmaf(h[-k - 2], row[k + 2], s2);
+            s3 = fmaf(h[-k - 3], row[k + 3], s3);
+        }
+        for (; k < nu; ++k)
+            s0 = fmaf(h[-k], row[k], s0);
+        out[base + i] = from_f32<TO>((s0 + s1) + (s2 + s3));
+    }
+}
+
+template <int DET, typename TI>
+hipError_t ramp_launch_out(const Params &p, const ViewRec *views, const TI *in, void *out,
+                           int out_dtype, dim3 grid, size_t lds, int window, float dbeta,
+                           int two_d, hipStream_t st)
+{
+    if (out_dtype == 1)
+        hipLaunchKernelGGL((ramp_kernel<DET, TI, __hip_bfloat16>), grid, dim3(kRampThreads), lds, st,
+                           p, views, in, (__hip_bfloat16 *)out, window, dbeta, two_d);
+    else if (out_dtype == 2)
+        hipLaunchKernelGGL((ramp_kernel<DET, TI, __half>), grid, dim3(kRampThreads), lds, st, p,
+                           views, in, (__half *)out, window, dbeta, two_d);
+    else
+        hipLaunchKernelGGL((ramp_kernel<DET, TI, float>), grid, dim3(kRampThreads), lds, st, p,
+                           views, in, (float *)out, window, dbeta, two_d);
+    return hipGetLastError();
+}
+
+template <int DET>
+hipError_t ramp_launch(const Params &p, const ViewRec *views, const void *in, int in_dtype,
+                       void *out, int out_dtype, dim3 grid, size_t lds, int window, float dbeta,
+                       int two_d, hipStream_t st)
+{
+    if (in_dtype == 1)
+        return ramp_launch_out<DET>(p, views, (const __hip_bfloat16 *)in, out, out_dtype, grid, lds,
+                                    window, dbeta, two_d, st);
+    if (in_dtype == 2)
+        return ramp_launch_out<DET>(p, views, (const __half *)in, out, out_dtype, grid, lds, window,
+                                    dbeta, two_d, st);
+    return ramp_launch_out<DET>(p, views, (const float *)in, out, out_dtype, grid, lds, window,
+                                dbeta, two_d, st);
+}
 
 // FP32 workspace -> BF16 / FP16 output (optionally accumulating into it).
 template <typename T>
@@ -1486,6 +1643,20 @@ hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *vi
                           int accumulate, hipStream_t st)
 {
     return dispatch<FwdOp>(c, p, c, views, volT, qscale, sino, batch, accumulate, st);
+}
+
+hipError_t launch_ramp(const Params &p, const LaunchCfg &c, const ViewRec *views, const void *in,
+                       int in_dtype, void *out, int out_dtype, int64_t batch, int window,
+                       float dbeta, hipStream_t st)
+{
+    const int two_d = c.geom == kFan2D ? 1 : 0;
+    dim3 grid((unsigned)(two_d ? p.nz : p.nv), (unsigned)p.n_views, (unsigned)batch);
+    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(float);
+    if (c.det == kCurved)
+        return ramp_launch<kCurved>(p, views, in, in_dtype, out, out_dtype, grid, lds, window, dbeta,
+                                    two_d, st);
+    return ramp_launch<kFlat>(p, views, in, in_dtype, out, out_dtype, grid, lds, window, dbeta, two_d,
+                              st);
 }
 
 hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,

@@ -19,6 +19,7 @@
 struct ctp_plan {
     ctp_geometry_desc g;     // sizes and kinds (pointers cleared)
     ctp_method method;
+    ctp_mode mode;
     int device;
     ctp::ViewRec *d_views;   // device table, n_views records
     ctp::LaunchCfg cfg;
@@ -134,7 +135,8 @@ const char *ctp_status_string(ctp_status s)
 
 const char *ctp_last_error(void) { return g_last_error.c_str(); }
 
-ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_plan **out)
+ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_mode mode,
+                           ctp_plan **out)
 {
     g_last_error.clear();
     if (desc == nullptr || out == nullptr)
@@ -147,6 +149,9 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         return fail(CTP_EINVAL, "unknown detector model");
     if (method != CTP_SF && method != CTP_DD)
         return fail(CTP_EINVAL, "unknown projector method");
+    if (mode != CTP_MODE_PROJ && mode != CTP_MODE_RECON)
+        return fail(CTP_EINVAL, "unknown projection mode");
+    const bool recon = mode == CTP_MODE_RECON;
     const bool two_d = g.kind == CTP_FAN2D;
     if (g.nx <= 0 || g.ny <= 0 || g.nu <= 0 || g.n_views <= 0 || (!two_d && (g.nz <= 0 || g.nv <= 0)))
         return fail(CTP_EINVAL, "sizes must be positive");
@@ -160,6 +165,8 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         return fail(CTP_EUNSUPPORTED, "non-circular scans use flat detectors only");
     if (method == CTP_DD && g.kind == CTP_CONE_NONCIRC)
         return fail(CTP_EUNSUPPORTED, "distance driven is built for circular scans only");
+    if (recon && (method != CTP_SF || g.kind == CTP_CONE_NONCIRC))
+        return fail(CTP_EUNSUPPORTED, "recon mode is built for SF on circular scans");
 
     struct {
         const char *name;
@@ -184,6 +191,8 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dy, hz = two_d ? 0.0 : 0.5 * nz * g.dz;
     std::vector<ctp::ViewRec> recs((size_t)g.n_views);
     double kmax = 0.0;   // widest transaxial footprint (columns) over all views
+    double rmax = 0.0;   // recon mode: largest SAD / W over views and volume corners
+    double mmin = 1e300; // smallest magnification over views and volume corners
 
     for (int b = 0; b < g.n_views; ++b) {
         const double ph = g.kind == CTP_CONE_NONCIRC ? phi.at(b) : 0.0;
@@ -207,16 +216,19 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         f.ve0 = two_d ? -0.5 * g.dv : -0.5 * nv * g.dv - vo.at(b);
 
         // every corner of the volume box must lie strictly in front of the source
-        double Wmin = 1e300, amax = 0.0;
+        double Wmin = 1e300, Wmax = 0.0, amax = 0.0;
         for (int c = 0; c < 8; ++c) {
             const Vec3 p{(c & 1) ? hx : -hx, (c & 2) ? hy : -hy, (c & 4) ? hz : -hz};
             const double W = dot(f.s - p, f.n);
             Wmin = std::fmin(Wmin, W);
+            Wmax = std::fmax(Wmax, W);
             amax = std::fmax(amax, std::fabs(dot(p - f.s, f.eu)));
         }
         const double D = dot(f.s - f.d, f.n);
         if (!(Wmin > 1e-6 * f.sdd))
             return fail(CTP_EINVAL, "part of the volume is at or behind the source in view " + std::to_string(b));
+        rmax = std::fmax(rmax, sad.at(b) / Wmin);
+        mmin = std::fmin(mmin, (g.det == CTP_DET_FLAT ? D : f.sdd) / std::hypot(Wmax, amax));
 
         // bound on the transaxial footprint width (columns): |grad u| * voxel extent
         const double grad = g.det == CTP_DET_FLAT ? D * (Wmin + amax) / (Wmin * Wmin) / g.du
@@ -258,6 +270,7 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         // distance driven: planes y = const when the detector normal is closer to y
         r.ydrv = std::fabs(f.n.y) >= std::fabs(f.n.x) ? 1 : 0;
         r.ddC = (float)(-(dms.z + f.ve0) / g.dv);
+        r.sad = (float)sad.at(b);
         if (method == CTP_DD) {
             // every column-edge ray must cross the driving planes
             for (int i = 0; i <= g.nu; i += (g.nu > 1 ? g.nu : 1)) {
@@ -284,6 +297,7 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     std::memset(plan, 0, sizeof(*plan));
     plan->g = g;
     plan->method = method;
+    plan->mode = mode;
     hipError_t e = hipGetDevice(&plan->device);
     if (e != hipSuccess) {
         delete plan;
@@ -305,7 +319,7 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     ctp::LaunchCfg &c = plan->cfg;
     c.geom = g.kind;
     c.det = g.det;
-    c.method = method;
+    c.method = recon ? ctp::kSFR : method;
     c.kcells = need <= 3 ? 3 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
     c.n_strips = (g.nu + ctp::kStripW - 1) / ctp::kStripW;
     c.n_row_chunks = (nv + ctp::kRowsMax - 1) / ctp::kRowsMax;
@@ -317,6 +331,13 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         const double lx = g.nx * g.dx, ly = g.ny * g.dy, lz = two_d ? 0.0 : nz * g.dz;
         c.acc_bound = method == CTP_SF ? (float)(4.0 * std::sqrt(lx * lx + ly * ly + lz * lz))
                                        : (float)(2.0 * (std::max(g.nx, g.ny) + 2));
+        if (recon) {
+            // normalised footprints: per layer of voxels across a ray the weights of one cell
+            // sum to at most 2 max(1, cell / voxel shadow) per axis; (nx + ny + 2) layers
+            const double fu = 2.0 * (1.0 + g.du / (mmin * std::min(g.dx, g.dy)));
+            const double fv = two_d ? 1.0 : 2.0 * (1.0 + g.dv / (mmin * g.dz));
+            c.acc_bound = (float)(2.0 * rmax * rmax * (g.nx + g.ny + 2) * fu * fv);
+        }
     }
 
     ctp::Params &p = plan->base;
@@ -417,7 +438,9 @@ BwdWs bwd_ws_layout(const ctp_plan *plan, int64_t batch, ctp_dtype vol_dtype, ct
     size_t vb = 0, sb = 0;
     ctp_plan_bytes(plan, CTP_F32, batch, &vb, &sb);
     BwdWs w;
-    w.scaled = !(plan->g.kind == CTP_FAN2D && plan->method == CTP_SF && sino_dtype == CTP_F32);
+    // the per-cell amplitude is 1 for 2D SF and in recon mode: FP32 sinograms are read as given
+    w.scaled = !(sino_dtype == CTP_F32 && (plan->mode == CTP_MODE_RECON ||
+                                           (plan->g.kind == CTP_FAN2D && plan->method == CTP_SF)));
     w.ysc_off = 0;
     w.vol_off = w.scaled ? align256(sb) : 0;
     w.total = w.vol_off + (vol_dtype == CTP_F32 ? 0 : vb);
@@ -571,6 +594,57 @@ ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sin
         e = ctp::launch_store_convert(out, vol, (int)vol_dtype, (int64_t)(vb / 4), accumulate, stream);
     }
     return finish(e, stream, "back projection");
+}
+
+ctp_status ctp_ramp_filter(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *out,
+                           ctp_dtype out_dtype, int64_t batch, ctp_window window,
+                           hipStream_t stream)
+{
+    g_last_error.clear();
+    if (plan == nullptr || sino == nullptr || out == nullptr)
+        return fail(CTP_EINVAL, "NULL plan or data pointer");
+    if (batch < 1)
+        return fail(CTP_EINVAL, "batch must be >= 1");
+    for (ctp_dtype d : {sino_dtype, out_dtype})
+        if (d != CTP_F32 && d != CTP_BF16 && d != CTP_F16)
+            return fail(CTP_EINVAL, "unknown dtype");
+    if (window != CTP_WINDOW_RAMLAK && window != CTP_WINDOW_SHEPP_LOGAN)
+        return fail(CTP_EINVAL, "unknown window");
+    if (plan->g.kind == CTP_CONE_NONCIRC)
+        return fail(CTP_EUNSUPPORTED, "the ramp filter weighting is defined for circular scans");
+    if (plan->g.nu > 5120)
+        return fail(CTP_EUNSUPPORTED, "more than 5120 detector columns");
+    if (plan->g.n_views > 65535)
+        return fail(CTP_EUNSUPPORTED, "more than 65535 views");
+    const bool two_d = plan->g.kind == CTP_FAN2D;
+    if (!two_d && batch > 65535)
+        return fail(CTP_EINVAL, "batch too large");
+    size_t in_b = 0, out_b = 0;
+    ctp_plan_bytes(plan, sino_dtype, batch, nullptr, &in_b);
+    ctp_plan_bytes(plan, out_dtype, batch, nullptr, &out_b);
+    const char *a0 = static_cast<const char *>(sino), *b0 = static_cast<const char *>(out);
+    if (a0 == b0 ? sino_dtype != out_dtype : (a0 < b0 + out_b && b0 < a0 + in_b))
+        return fail(CTP_EINVAL, "input and output overlap (only exact in-place with one type is allowed)");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+        return fail(CTP_EINVAL, "plan was created on another device");
+    ctp::Params p = plan->base;
+    const ctp_geometry_desc &g = plan->g;
+    if (two_d) {
+        p.nz = (int)batch;
+        p.nv = (int)batch;
+        p.sino_row_stride = (int64_t)g.n_views * g.nu;
+        p.sino_view_stride = g.nu;
+        p.sino_b_stride = 0;
+    } else {
+        p.sino_row_stride = g.nu;
+        p.sino_view_stride = (int64_t)g.nv * g.nu;
+        p.sino_b_stride = (int64_t)g.n_views * g.nv * g.nu;
+    }
+    const float dbeta = (float)(2.0 * 3.14159265358979323846 / g.n_views);
+    hipError_t e = ctp::launch_ramp(p, plan->cfg, plan->d_views, sino, (int)sino_dtype, out,
+                                    (int)out_dtype, two_d ? 1 : batch, (int)window, dbeta, stream);
+    return finish(e, stream, "ramp filter");
 }
 
 }  // extern "C"

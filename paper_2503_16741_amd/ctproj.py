@@ -27,13 +27,18 @@ CTP_DET_FLAT, CTP_DET_CURVED = 0, 1
 CTP_SF, CTP_DD = 0, 1
 CTP_F32, CTP_BF16, CTP_F16 = 0, 1, 2
 CTP_FORWARD, CTP_BACKWARD = 0, 1
+CTP_MODE_PROJ, CTP_MODE_RECON = 0, 1
+CTP_WINDOW_RAMLAK, CTP_WINDOW_SHEPP_LOGAN = 0, 1
 
 KIND = {"fan2d": CTP_FAN2D, "cone": CTP_CONE_CIRC, "cone_noncirc": CTP_CONE_NONCIRC}
 DET = {"flat": CTP_DET_FLAT, "curved": CTP_DET_CURVED}
 METHOD = {"sf": CTP_SF, "dd": CTP_DD}
+MODE = {"proj": CTP_MODE_PROJ, "recon": CTP_MODE_RECON}
+WINDOW = {"ram-lak": CTP_WINDOW_RAMLAK, "shepp-logan": CTP_WINDOW_SHEPP_LOGAN}
 
 EXPORTED = ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes", "ctp_workspace_bytes",
-            "ctp_project", "ctp_backproject", "ctp_status_string", "ctp_last_error")
+            "ctp_project", "ctp_backproject", "ctp_ramp_filter", "ctp_status_string",
+            "ctp_last_error")
 # include/ctserve.h
 EXPORTED_SERVER = ("ctp_server_create", "ctp_server_submit", "ctp_server_wait",
                    "ctp_server_query", "ctp_server_info", "ctp_server_release",
@@ -89,7 +94,10 @@ def lib() -> ctypes.CDLL:
                     "(or __graft_entry__.build()); there is no CPU fallback")
             L = ctypes.CDLL(LIB_PATH)
             vp, sz, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
-            L.ctp_plan_create.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.POINTER(vp)]
+            L.ctp_plan_create.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(vp)]
+            L.ctp_ramp_filter.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i64, ctypes.c_int,
+                                          vp]
             L.ctp_plan_destroy.argtypes = [vp]
             L.ctp_plan_bytes.argtypes = [vp, ctypes.c_int, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)]
             L.ctp_workspace_bytes.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, i64,
@@ -99,7 +107,7 @@ def lib() -> ctypes.CDLL:
             L.ctp_backproject.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i64, ctypes.c_int,
                                           vp, sz, vp]
             for f in ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes",
-                      "ctp_workspace_bytes", "ctp_project", "ctp_backproject"):
+                      "ctp_workspace_bytes", "ctp_project", "ctp_backproject", "ctp_ramp_filter"):
                 getattr(L, f).restype = ctypes.c_int
             u64 = ctypes.c_uint64
             L.ctp_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
@@ -145,10 +153,11 @@ def _check(st: int, where: str):
 class Plan:
     """Owner of a ``ctp_plan*`` plus the geometry it was built from."""
 
-    def __init__(self, handle: int, geom: Geometry, method: str):
+    def __init__(self, handle: int, geom: Geometry, method: str, mode: str = "proj"):
         self.handle = ctypes.c_void_p(handle)
         self.geom = geom
         self.method = method
+        self.mode = mode
         self._ws = {}
 
     def close(self):
@@ -181,13 +190,13 @@ def make_desc(geom: Geometry):
     return d, keep
 
 
-def ctp_plan_create(geom: Geometry, method: str = "sf") -> Plan:
+def ctp_plan_create(geom: Geometry, method: str = "sf", mode: str = "proj") -> Plan:
     d, keep = make_desc(geom)
     out = ctypes.c_void_p()
-    _check(lib().ctp_plan_create(ctypes.byref(d), METHOD[method], ctypes.byref(out)),
+    _check(lib().ctp_plan_create(ctypes.byref(d), METHOD[method], MODE[mode], ctypes.byref(out)),
            "ctp_plan_create")
     del keep
-    return Plan(out.value, geom, method)
+    return Plan(out.value, geom, method, mode)
 
 
 def ctp_plan_destroy(plan: Plan):
@@ -293,6 +302,32 @@ def ctp_backproject(plan: Plan, sino, vol, accumulate: bool = False, workspace=N
                                  ws.data_ptr() if ws is not None else None, nbytes,
                                  _stream_handle(stream)), "ctp_backproject")
     return vol
+
+
+def ctp_ramp_filter(plan: Plan, sino, out, window: str = "ram-lak", stream=None):
+    """out = cosine-weighted, ramp-filtered sino (FBP / FDK weighting of a full circular scan);
+    out may be sino itself when the storage types agree."""
+    g = plan.geom
+    _check_tensor(sino, g.sino_shape, "sino")
+    _check_tensor(out, g.sino_shape, "out")
+    batch = sino.numel() // int(np.prod(g.sino_shape))
+    if out.numel() != sino.numel():
+        raise ValueError("sino and out sizes differ")
+    _check(lib().ctp_ramp_filter(plan.handle, sino.data_ptr(), _dtype_code(sino), out.data_ptr(),
+                                 _dtype_code(out), batch, WINDOW[window], _stream_handle(stream)),
+           "ctp_ramp_filter")
+    return out
+
+
+def fbp(plan: Plan, sino, window: str = "ram-lak", out_dtype=None):
+    """Filtered back projection (2D fan beam) / FDK (3D circular cone beam) with a recon-mode
+    plan: ramp filter into an FP32 buffer, then the recon-mode back projection."""
+    import torch
+    if plan.mode != "recon":
+        raise ValueError("fbp needs a plan created with mode='recon'")
+    q = torch.empty(sino.shape, dtype=torch.float32, device=sino.device)
+    ctp_ramp_filter(plan, sino, q, window)
+    return backproject(plan, q, out_dtype=out_dtype or torch.float32)
 
 
 def project(plan: Plan, vol, out_dtype=None):

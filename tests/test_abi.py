@@ -30,7 +30,7 @@ def declared_functions():
 
 def test_exports_every_declared_function(ct):
     names = declared_functions()
-    assert len(names) == 8
+    assert len(names) == 9
     assert set(names) == set(ct.EXPORTED)
     lib = ct.lib()
     for n in names:
@@ -104,10 +104,25 @@ def test_plan_validation_without_device(ct, over, method, status):
     assert ct.ctp_last_error() != ""
 
 
+@pytest.mark.parametrize("over,method,status", [
+    (dict(), "dd", -2),                               # recon mode is SF only
+    (dict(kind="cone_noncirc"), "sf", -2),            # and circular scans only
+])
+def test_recon_mode_validation_without_device(ct, over, method, status):
+    with pytest.raises(ct.CtpError) as e:
+        ct.ctp_plan_create(geom(**over), method, "recon")
+    assert e.value.status == status
+    L = ct.lib()
+    d, keep = ct.make_desc(geom())
+    out = ctypes.c_void_p()
+    assert L.ctp_plan_create(ctypes.byref(d), 0, 7, ctypes.byref(out)) == ct.CTP_EINVAL
+    assert L.ctp_ramp_filter(None, None, 0, None, 0, 1, 0, None) == ct.CTP_EINVAL
+
+
 def test_null_arguments(ct):
     lib = ct.lib()
     out = ctypes.c_void_p()
-    assert lib.ctp_plan_create(None, 0, ctypes.byref(out)) == ct.CTP_EINVAL
+    assert lib.ctp_plan_create(None, 0, 0, ctypes.byref(out)) == ct.CTP_EINVAL
     assert lib.ctp_plan_destroy(None) == ct.CTP_OK
     assert lib.ctp_project(None, None, 0, None, 0, 1, 0, None, 0, None) == ct.CTP_EINVAL
     assert lib.ctp_backproject(None, None, 0, None, 0, 1, 0, None, 0, None) == ct.CTP_EINVAL
@@ -119,10 +134,11 @@ def test_projector_module_arguments():
     """Projector(geom, mode, method, direction) validates its strings without a device."""
     from paper_2503_16741_amd.autograd import Projector
     g = geom()
-    with pytest.raises(NotImplementedError):
-        Projector(g, "recon", "SF", "forward")
+    with pytest.raises(ValueError):
+        Projector(g, "fbp", "SF", "forward")
     with pytest.raises(NotImplementedError):
         Projector(g, "proj", "VD", "forward")
+    assert Projector(g, "recon", "SF", "backward").mode == "recon"
     with pytest.raises(ValueError):
         Projector(g, "proj", "SF", "sideways")
     p = Projector(g, "proj", "dd", "backward")
