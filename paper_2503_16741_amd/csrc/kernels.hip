@@ -491,11 +491,13 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
            af - an - bn <= -m && fmaf(bf - bn, zl, af - an - bn) <= -m;
 }
 
-template <int K, bool NORM>
+// NC: the column's number of footprint cells in this strip (weights w[0..NC-1]); the emit of
+// row j (j = -1 lands in the guard row below row 0) adds round(row value x w_k) to the NC cells.
+template <int K, int NC, bool NORM>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
-                                           const float (&w)[K], int nc, int *accs, int SW,
-                                           int R, int lane)
+                                           const float (&w)[K], int *accs, int SW, int R,
+                                           int lane)
 {
     const float fR = (float)R;
     for (int zb = 0; zb < nz; zb += 256) {
@@ -534,32 +536,26 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
         uint32_t Cprev = 0u, S = 0u;
         float vm1 = 0.0f;
         auto emit = [&](int t, uint32_t C) {
-            const int j = t - 1;
-            if (j >= 0) {
-                const float rv = (float)(int)(C - Cprev);
-                int *a = accs + j * SW;
+            const float rv = (float)(int)(C - Cprev);
+            int *a = accs + (t - 1) * SW;
 #pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k < nc)
-                        atomicAdd(a + k, to_fixed(rv * w[k]));
-            }
+            for (int k = 0; k < NC; ++k)
+                atomicAdd(a + k, to_fixed(rv * w[k]));
             Cprev = C;
         };
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q < nq) {
+                // branch-free C(t) - S over face q and voxel q's plateau:
+                //   v_q (min(t - p, w)^2 / (2w) + max(t - q, 0)) - v_{q-1} max(q - t, 0)^2 / (2w)
                 const float pz = p[q], qz = qf[q], wz = qz - pz;
+                const float h = wz > 1e-12f ? 0.5f * fast_rcp(wz) : 0.0f;
                 const int te = min((int)ceilf(fminf(p[q + 1], fR + 1.0f)) - 1, R);
                 for (int t = tp + 1; t <= te; ++t) {
                     const float ft = (float)t;
-                    float local;
-                    if (ft < qz && wz > 1e-12f) {
-                        const float h = 0.5f * fast_rcp(wz);
-                        const float d1 = ft - pz, d2 = qz - ft;
-                        local = (v[q] * d1 * d1 - vm1 * d2 * d2) * h;
-                    } else {
-                        local = v[q] * (0.5f * wz + (ft - qz));
-                    }
+                    const float d1 = fminf(ft - pz, wz), d2 = fmaxf(qz - ft, 0.0f);
+                    const float local = fmaf(v[q], fmaf(d1 * d1, h, fmaxf(ft - qz, 0.0f)),
+                                             -vm1 * (d2 * d2 * h));
                     emit(t, S + (uint32_t)__float2int_rn(local));
                 }
                 tp = max(tp, te);
@@ -568,23 +564,39 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                 vm1 = v[q];
             }
         }
-        // above the run's top face
+        // above the run's top face: S minus the falling ramp of its last voxel
         {
             const float pt = p[nq], qt = qf[nq], wt = qt - pt;
+            const float h = wt > 1e-12f ? 0.5f * fast_rcp(wt) : 0.0f;
             const int te = min((int)floorf(fminf(qt, fR)) + 1, R);
             for (int t = tp + 1; t <= te; ++t) {
-                const float ft = (float)t;
-                float local = 0.0f;
-                if (ft < qt && wt > 1e-12f) {
-                    const float d2 = qt - ft;
-                    local = -vm1 * d2 * d2 * 0.5f * fast_rcp(wt);
-                }
-                emit(t, S + (uint32_t)__float2int_rn(local));
+                const float d2 = fmaxf(qt - (float)t, 0.0f);
+                emit(t, S + (uint32_t)__float2int_rn(-vm1 * (d2 * d2 * h)));
             }
         }
     }
 }
 
+// Dispatch the SF run on the column's cell count (uniform across the wavefront).
+template <int K, bool NORM>
+__device__ __forceinline__ void sf_fwd_run_nc(const float *__restrict__ colp, int nz, float an,
+                                              float bn, float af, float bf,
+                                              const float (&w)[K], int nc, int *accs, int SW,
+                                              int R, int lane)
+{
+    if constexpr (K <= 4) {
+        switch (nc) {
+        case 1: sf_fwd_run<K, 1, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 2: sf_fwd_run<K, 2, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 3: sf_fwd_run<K, (K >= 3 ? 3 : K), NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        default: sf_fwd_run<K, K, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        }
+    } else {
+        // wide footprints: all K cells (weights past nc are zero; the extra cells stay within
+        // the strip row plus its padding)
+        sf_fwd_run<K, K, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane);
+    }
+}
 
 // DD forward, circular: for column k of the footprint the slices' mapped z-intervals
 // [zeta_z, zeta_{z+1}] (rows, zeta_z = al_k + be_k z) tile the axis, so the run's integral up to
@@ -624,10 +636,8 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
             int tp = max((int)floorf(zt[0]), -1);
             uint32_t Cprev = 0u, S = 0u;
             int *ak = accs + k;
-            auto emit = [&](int t, uint32_t C) {
-                const int j = t - 1;
-                if (j >= 0)
-                    atomicAdd(ak + j * SW, to_fixed((float)(int)(C - Cprev) * fx[k]));
+            auto emit = [&](int t, uint32_t C) {   // t - 1 = -1 lands in the guard row
+                atomicAdd(ak + (t - 1) * SW, to_fixed((float)(int)(C - Cprev) * fx[k]));
                 Cprev = C;
             };
 #pragma unroll
@@ -668,7 +678,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     // 31 bits); contributions are converted to integers and summed, which is order
     // independent, so an item's result is bitwise repeatable and does not depend on the
     // other items of the batch.  qscale[2 b + 1] = 2^-S undoes the scale on write-out.
-    extern __shared__ int acc[];             // [R][kStripW + 1]
+    extern __shared__ int acc_mem[];         // guard row, [R][kStripW + 1], kMaxCells of padding
     __shared__ int s_count, s_next;
     __shared__ unsigned short s_list[kListCap];
 
@@ -692,8 +702,9 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     const ViewRec V = views[view];
     constexpr int SW = kStripW + 1;
 
-    for (int e = threadIdx.x; e < R * SW; e += blockDim.x)
-        acc[e] = 0;
+    int *acc = acc_mem + SW;                 // row -1 (the guard) absorbs emits below row 0
+    for (int e = threadIdx.x; e < (R + 1) * SW + kMaxCells; e += blockDim.x)
+        acc_mem[e] = 0;
 
     const float hz = 0.5f * P.dz;
     const float zb0 = P.z0 - hz - V.s[2];               // bottom face of slice 0, minus z_src
@@ -782,8 +793,8 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
                         if (sf_fast_ok(s_an, s_bn, s_af, s_bf, P.nz)) {
-                            sf_fwd_run<K, METHOD == kSFR>(colp, P.nz, s_an, s_bn, s_af, s_bf, sw,
-                                                          s_nc, accs, SW, R, lane);
+                            sf_fwd_run_nc<K, METHOD == kSFR>(colp, P.nz, s_an, s_bn, s_af, s_bf,
+                                                             sw, s_nc, accs, SW, R, lane);
                             continue;
                         }
                     }
@@ -1348,7 +1359,7 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
 {
     const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
     const int R = min(kRowsMax, rows_total);
-    size_t lds = (size_t)R * (kStripW + 1) * sizeof(int);
+    size_t lds = ((size_t)(R + 1) * (kStripW + 1) + kMaxCells) * sizeof(int);
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
     dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.n_views),
               (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
