@@ -479,8 +479,8 @@ __device__ __forceinline__ void box_u_range(const ViewRec &V, const Params &P, f
 // gets C(j+1) - C(j), which equals the sum of the run's voxels' G(j+1) - G(j).  Runs are
 // independent (their contributions add), so each lane takes a run of 4 slices: neighbouring
 // lanes emit different rows at the same time, and no lane needs another lane's data.
-// C is kept in 32-bit fixed point (the column values arrive pre-scaled by the item's 2^S)
-// with wrapping arithmetic; rows are exact differences.
+// The column values arrive pre-scaled by the item's 2^S; each row's difference is rounded into
+// the 32-bit fixed-point accumulators.
 __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float bf, int nz)
 {
     // faces z and z+1 disjoint for every z: an + bn z <= af + bf (z+1) and vice versa
@@ -533,10 +533,12 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                     v[q] *= fdiv(2.0f, (p[q + 1] + qf[q + 1]) - (p[q] + qf[q]));
         }
         int tp = max((int)floorf(p[0]), -1);     // last edge handled (C = 0 at floor(p0))
-        uint32_t Cprev = 0u, S = 0u;
+        // C and the prefix S stay in FP32: a run holds four slices, so they are sums of a few
+        // terms and the row differences C(j+1) - C(j) lose at most a few ulps of x.
+        float Cprev = 0.0f, S = 0.0f;
         float vm1 = 0.0f;
-        auto emit = [&](int t, uint32_t C) {
-            const float rv = (float)(int)(C - Cprev);
+        auto emit = [&](int t, float C) {
+            const float rv = C - Cprev;
             int *a = accs + (t - 1) * SW;
 #pragma unroll
             for (int k = 0; k < NC; ++k)
@@ -556,11 +558,11 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                     const float d1 = fminf(ft - pz, wz), d2 = fmaxf(qz - ft, 0.0f);
                     const float local = fmaf(v[q], fmaf(d1 * d1, h, fmaxf(ft - qz, 0.0f)),
                                              -vm1 * (d2 * d2 * h));
-                    emit(t, S + (uint32_t)__float2int_rn(local));
+                    emit(t, S + local);
                 }
                 tp = max(tp, te);
                 const float area = 0.5f * ((p[q + 1] + qf[q + 1]) - (pz + qz));
-                S += (uint32_t)__float2int_rn(v[q] * area);
+                S = fmaf(v[q], area, S);
                 vm1 = v[q];
             }
         }
@@ -571,7 +573,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
             const int te = min((int)floorf(fminf(qt, fR)) + 1, R);
             for (int t = tp + 1; t <= te; ++t) {
                 const float d2 = fmaxf(qt - (float)t, 0.0f);
-                emit(t, S + (uint32_t)__float2int_rn(-vm1 * (d2 * d2 * h)));
+                emit(t, fmaf(-vm1, d2 * d2 * h, S));
             }
         }
     }
@@ -634,10 +636,10 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
             if (zt[nq] < 0.0f || zt[0] >= fR)
                 continue;
             int tp = max((int)floorf(zt[0]), -1);
-            uint32_t Cprev = 0u, S = 0u;
+            float Cprev = 0.0f, S = 0.0f;          // FP32 prefix of the run (a few terms)
             int *ak = accs + k;
-            auto emit = [&](int t, uint32_t C) {   // t - 1 = -1 lands in the guard row
-                atomicAdd(ak + (t - 1) * SW, to_fixed((float)(int)(C - Cprev) * fx[k]));
+            auto emit = [&](int t, float C) {      // t - 1 = -1 lands in the guard row
+                atomicAdd(ak + (t - 1) * SW, to_fixed((C - Cprev) * fx[k]));
                 Cprev = C;
             };
 #pragma unroll
@@ -645,9 +647,9 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
                 if (q < nq) {
                     const int te = min((int)ceilf(fminf(zt[q + 1], fR + 1.0f)) - 1, R);
                     for (int t = tp + 1; t <= te; ++t)
-                        emit(t, S + (uint32_t)__float2int_rn(v[q] * ((float)t - zt[q])));
+                        emit(t, fmaf(v[q], (float)t - zt[q], S));
                     tp = max(tp, te);
-                    S += (uint32_t)__float2int_rn(v[q] * (zt[q + 1] - zt[q]));
+                    S = fmaf(v[q], zt[q + 1] - zt[q], S);
                 }
             }
             const int te = min((int)floorf(fminf(zt[nq], fR)) + 1, R);
@@ -987,19 +989,21 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
                                             float an, float bn, float af, float bf, int zc0,
                                             int nq, float (&acc)[NQ])
 {
-    int cidx[K];
+    // 32-bit element offsets within the view (a view holds < 2^31 cells); rows outside
+    // [0, rows) read a clamped, in-bounds row and contribute zero.
+    const uint32_t rs = (uint32_t)row_stride;
+    uint32_t cidx[K];
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        cidx[k] = min(cs + k, nu - 1);          // weights are 0 past the footprint
+        cidx[k] = (uint32_t)min(cs + k, nu - 1);          // weights are 0 past the footprint
     auto load_row = [&](int j) -> float {
+        const int jj = min(max(j, 0), rows - 1);
+        const uint32_t off = (uint32_t)jj * rs;
         float r = 0.0f;
-        if (j >= 0 && j < rows) {
-            const float *yr = yv + (int64_t)j * row_stride;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                r = fmaf(w[k], yr[cidx[k]], r);
-        }
-        return r;
+        for (int k = 0; k < K; ++k)
+            r = fmaf(w[k], yv[off + cidx[k]], r);
+        return (j >= 0 && j < rows) ? r : 0.0f;
     };
     const float fr = (float)rows;
     const float zs = (float)zc0;
@@ -1021,12 +1025,11 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
                 rn = load_row(jc + 1);
             }
             const float R = fmaf(q - (float)jc, rc, RP);
-            float J = 0.0f;
-            if (w > 1e-12f) {
-                const float a = (float)jc - p;              // > 0 when the face straddles row edge jc
-                const float h = 0.5f * fast_rcp(w);
-                J = a > 0.0f ? fmaf(rp - rc, a * a * h, rc * 0.5f * w) : rc * 0.5f * w;
-            }
+            // ramp-weighted integral of r over the face (branch-free: a <= 0 when the face lies
+            // within row jc, w <= eps for a degenerate face)
+            const float a = fmaxf((float)jc - p, 0.0f);
+            const float h = w > 1e-12f ? 0.5f * fast_rcp(w) : 0.0f;
+            const float J = fmaf(rp - rc, a * a * h, rc * 0.5f * w);
             const float D = R - J;
             if (f > 0) {
                 if constexpr (NORM)   // recon mode: divide by the slice's trapezoid area
