@@ -554,10 +554,12 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                 const float h = wz > 1e-12f ? 0.5f * fast_rcp(wz) : 0.0f;
                 const int te = min((int)ceilf(fminf(p[q + 1], fR + 1.0f)) - 1, R);
                 for (int t = tp + 1; t <= te; ++t) {
+                    // with u = t - q and e = max(u, 0): min(t - p, w) = (t - p) - e and
+                    // max(q - t, 0) = e - u (no min/max of loop-invariant operands)
                     const float ft = (float)t;
-                    const float d1 = fminf(ft - pz, wz), d2 = fmaxf(qz - ft, 0.0f);
-                    const float local = fmaf(v[q], fmaf(d1 * d1, h, fmaxf(ft - qz, 0.0f)),
-                                             -vm1 * (d2 * d2 * h));
+                    const float u = ft - qz, e = fmaxf(u, 0.0f);
+                    const float d1 = (ft - pz) - e, d2 = e - u;
+                    const float local = fmaf(v[q], fmaf(d1 * d1, h, e), -vm1 * (d2 * d2 * h));
                     emit(t, S + local);
                 }
                 tp = max(tp, te);
@@ -1200,10 +1202,50 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                     }
                 } else {
                     float al[K], be[K];
+                    bool walk = true;
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         al[k] = fmaf(bz[k], zb0, V.ddC);
                         be[k] = bz[k] * P.dz;
+                        walk = walk && !(k < nc && !(be[k] > 0.0f));
+                    }
+                    if (CTP_BWD_FAST && walk) {
+                        // Footprint column k maps slice z onto rows [zeta_z, zeta_{z+1}],
+                        // zeta_f = al_k + be_k f, which tile the axis; the slice's gather is
+                        // R_k(zeta_{z+1}) - R_k(zeta_z), R_k the running integral of the column's
+                        // rows (clamped to the detector), so each row is loaded once.
+                        const int nq = min(kZChunk, nzv - zc0);
+                        const float fr = (float)rows_total;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            if (k >= nc)
+                                break;
+                            const float *yk = yc0 + k;
+                            const uint32_t rs = (uint32_t)P.sino_row_stride;
+                            float RP = 0.0f, Dprev = 0.0f, rc = 0.0f;
+                            int jc = 0;
+#pragma unroll
+                            for (int f = 0; f <= kZChunk; ++f) {
+                                if (f <= nq) {
+                                    const float t = fminf(fmaxf(fmaf(be[k], (float)(zc0 + f), al[k]), 0.0f), fr);
+                                    const int jt = min((int)t, rows_total - 1);
+                                    if (f == 0) {
+                                        jc = jt;
+                                        rc = yk[(uint32_t)jc * rs];
+                                    }
+                                    while (jc < jt) {
+                                        RP += rc;
+                                        ++jc;
+                                        rc = yk[(uint32_t)jc * rs];
+                                    }
+                                    const float D = fmaf(t - (float)jc, rc, RP);
+                                    if (f > 0)
+                                        acc[f - 1] = fmaf(fx[k], D - Dprev, acc[f - 1]);
+                                    Dprev = D;
+                                }
+                            }
+                        }
+                        continue;
                     }
 #pragma unroll
                     for (int q = 0; q < kZChunk; ++q) {
