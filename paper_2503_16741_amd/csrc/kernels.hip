@@ -985,14 +985,16 @@ __device__ __forceinline__ bool sf_bwd_fast_ok(float an, float bn, float af, flo
     return disjoint && narrow;
 }
 
-template <int K, int NQ, bool NORM>
+// INSIDE: every row the walk loads (floor(p_first) .. floor(q_last) + 1) lies on the detector
+// and the K footprint columns cs .. cs + K - 1 exist, so rows are read through a running row
+// pointer (one add per row, the K columns at immediate offsets); otherwise rows are read at
+// clamped, in-bounds indices (32-bit offsets within the view) and outside rows count zero.
+template <int K, int NQ, bool NORM, bool INSIDE>
 __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_t row_stride,
                                             int cs, int nu, int rows, const float (&w)[K],
                                             float an, float bn, float af, float bf, int zc0,
                                             int nq, float (&acc)[NQ])
 {
-    // 32-bit element offsets within the view (a view holds < 2^31 cells); rows outside
-    // [0, rows) read a clamped, in-bounds row and contribute zero.
     const uint32_t rs = (uint32_t)row_stride;
     uint32_t cidx[K];
 #pragma unroll
@@ -1010,7 +1012,25 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
     const float fr = (float)rows;
     const float zs = (float)zc0;
     int jc = (int)floorf(fminf(fmaxf(fminf(fmaf(bn, zs, an), fmaf(bf, zs, af)), -1.0f), fr));
-    float rc = load_row(jc), rn = load_row(jc + 1), rp = 0.0f, RP = 0.0f, Dprev = 0.0f;
+    const float *rowp = yv + cs + (int64_t)(jc + 1) * row_stride;   // row jc + 1 (INSIDE)
+    auto load_next = [&]() -> float {
+        if constexpr (INSIDE) {
+            float r = 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                r = fmaf(w[k], rowp[k], r);
+            return r;
+        } else {
+            return load_row(jc + 1);
+        }
+    };
+    float rc = INSIDE ? 0.0f : load_row(jc);
+    if constexpr (INSIDE) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            rc = fmaf(w[k], rowp[k - (int64_t)row_stride], rc);
+    }
+    float rn = load_next(), rp = 0.0f, RP = 0.0f, Dprev = 0.0f;
     float mprev = 0.0f;                               // p + q of the previous face (NORM)
 #pragma unroll
     for (int f = 0; f <= NQ; ++f) {
@@ -1024,7 +1044,9 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
                 rp = rc;
                 rc = rn;
                 ++jc;
-                rn = load_row(jc + 1);
+                if constexpr (INSIDE)
+                    rowp += row_stride;
+                rn = load_next();
             }
             const float R = fmaf(q - (float)jc, rc, RP);
             // ramp-weighted integral of r over the face (branch-free: a <= 0 when the face lies
@@ -1119,9 +1141,20 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                     const float af = fmaf(col.Af, zb0, V.cv), bf = col.Af * P.dz;
                     const int nq = min(kZChunk, nzv - zc0);
                     if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + nq - 1)) {
-                        sf_bwd_fast<K, kZChunk, METHOD == kSFR>(yv, P.sino_row_stride, cs, P.nu,
-                                                                rows_total, w, an, bn, af, bf,
-                                                                zc0, nq, acc);
+                        // rows loaded: floor(p at zc0) .. floor(q at zc0 + nq) + 1
+                        const float z0f = (float)zc0, z1f = (float)(zc0 + nq);
+                        const float plo = fminf(fmaf(bn, z0f, an), fmaf(bf, z0f, af));
+                        const float qhi = fmaxf(fmaf(bn, z1f, an), fmaf(bf, z1f, af));
+                        const bool inside = plo >= 0.0f && qhi < (float)(rows_total - 2) &&
+                                            cs + K <= P.nu;
+                        if (inside)
+                            sf_bwd_fast<K, kZChunk, METHOD == kSFR, true>(
+                                yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
+                                zc0, nq, acc);
+                        else
+                            sf_bwd_fast<K, kZChunk, METHOD == kSFR, false>(
+                                yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
+                                zc0, nq, acc);
                         continue;
                     }
 #pragma unroll
