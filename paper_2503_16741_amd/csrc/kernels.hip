@@ -662,6 +662,26 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
 }
 
 constexpr int kListCap = 2048;
+constexpr int kLaneItems = 32;   // 2D batches up to this size: each lane scatters its own pixel
+
+// 2D forward with a small batch: lane = pixel, looping over the batch items itself (the
+// broadcast scheme puts the items on the lanes, which leaves most lanes idle for a few items).
+template <int K>
+__device__ __forceinline__ void fan2d_lane_scatter(const float *__restrict__ colp, int zbeg,
+                                                   int zend, int r0, const float (&w)[K],
+                                                   int nc, int *accs, int SW)
+{
+    if (nc <= 0)
+        return;
+    for (int z = zbeg; z < zend; ++z) {
+        const float val = colp[z];
+        int *a = accs + (z - r0) * SW;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k < nc)
+                atomicAdd(a + k, to_fixed(val * w[k]));
+    }
+}
 
 // ============================================================================================
 // Forward projector
@@ -779,6 +799,13 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                 const int nc = valid ? max(ce - cs + 1, 0) : 0;
                 float w[K];
                 sf_cell_weights<K>(col, cs, nc, P.eps, w);
+                if constexpr (GEOM == kFan2D) {
+                    if (zend - zbeg <= kLaneItems) {
+                        fan2d_lane_scatter<K>(volb + ((int64_t)iy * P.nx + ix) * colstride, zbeg,
+                                              zend, r0, w, nc, acc + (cs - i_lo), SW);
+                        continue;
+                    }
+                }
                 const float an = fmaf(col.An, zb0, V.cv - (float)r0), bn = col.An * P.dz;
                 const float af = fmaf(col.Af, zb0, V.cv - (float)r0), bf = col.Af * P.dz;
                 uint64_t m = __ballot(nc > 0);
@@ -885,6 +912,13 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                 const int nc = valid ? max(ce - cs + 1, 0) : 0;
                 float fx[K], bz[K];
                 dd_cell_weights<DET, K>(V, P, xc, yc, cs, nc, fx, bz);
+                if constexpr (GEOM == kFan2D) {
+                    if (zend - zbeg <= kLaneItems) {
+                        fan2d_lane_scatter<K>(volb + ((int64_t)iy * P.nx + ix) * colstride, zbeg,
+                                              zend, r0, fx, nc, acc + (cs - i_lo), SW);
+                        continue;
+                    }
+                }
                 uint64_t m = __ballot(nc > 0);
                 while (m) {
                     const int c = __ffsll((unsigned long long)m) - 1;
