@@ -64,7 +64,8 @@ def load_traffic(kernel_name):
 
 
 KERNEL_KEYS = {"fwd_kernel": "sf_forward", "bwd_kernel": "sf_backward",
-               "transpose_zfast_kernel": "transpose", "amp_scale_kernel": "amp_scale"}
+               "transpose_zfast_kernel": "transpose", "amp_scale_kernel": "amp_scale",
+               "item_max_kernel": "item_max"}
 
 
 def summarize_traffic(fetch_csv, write_csv):
