@@ -32,9 +32,12 @@ METRIC = "GUPS (voxel×view updates/s) SF fwd+back at 256³×360 views; p99 late
 SF_ROWS_PER_VV = 2.007
 SF_NNZ_PER_VV = 4.461
 SF_OPS_PER_VV = 4 + 6 + 10 + 13 * (SF_ROWS_PER_VV - 1) + SF_ROWS_PER_VV + 2 * SF_NNZ_PER_VV + 0.4
-# FP32 VALU issue peak: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s (one op per
-# lane per clock; packed-FP32 dual issue is not used).
-VALU_PEAK = 256 * 64 * 2.4e9
+# FP32 VALU peak: the published 157.3 TFLOP/s is 128 FP32 lanes per clock per CU (an FMA being
+# two flops), i.e. 256 CU x 128 x 2.4 GHz = 78.6e12 FP32 operations per second counting an
+# FMA, add, multiply or min/max as one operation -- the unit of the count above.  (A dependent
+# v_fma_f32 chain sustains half of that; two-operand v_fmac_f32 streams sustain more than half,
+# measured 42e12/s in the ramp filter.)
+VALU_PEAK = 256 * 128 * 2.4e9
 HBM_PEAK = 8.0e12
 
 WORKLOAD = ("3D circular cone-beam SF-TT forward+back: 256^3 FP32 at 0.5 mm (20 seeded "
@@ -272,6 +275,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dd", action="store_true")
     ap.add_argument("--no-recon", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB device copy, one SF forward and one SF back projection "
@@ -381,6 +385,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / VALU_PEAK, 4),
             "ops_per_voxel_view": round(SF_OPS_PER_VV, 2),
+            "op_unit": "FP32 VALU operation (an FMA counts once); peak = 157.3 TFLOP/s / 2",
             "traffic": traffic,
             "hbm_frac_algorithmic": round((vol.numel() + sino.numel()) * 4 / (dom_ms * 1e-3) / HBM_PEAK, 5),
         },
@@ -396,6 +401,42 @@ def main():
                      "back_ms": round(float(bwd_d.mean()), 4),
                      "p99_ms": round(float(np.percentile(pair_d, 99)), 4)}
         plan_dd.close()
+
+    if not args.no_variants:
+        # the other scan geometries at their full sizes: curved detector (512x512x256, 720
+        # views, 736x64) and non-circular poses (384^3, 500 views, 640x480, per-view jitter)
+        out["variants"] = {}
+        for name, gv, method in (("curved_512x512x256_720v", synth.curved_c3(), "sf"),
+                                 ("noncirc_384c_500v", synth.noncirc_c4(), "sf")):
+            pv = ctproj.ctp_plan_create(gv, method)
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(5)
+            xv = torch.rand(gv.vol_shape, generator=gen, device=dev)
+            yv = torch.empty(gv.sino_shape, dtype=torch.float32, device=dev)
+            bv = torch.empty_like(xv)
+            ctproj.ctp_project(pv, xv, yv)
+            ctproj.ctp_backproject(pv, yv, bv)
+            torch.cuda.synchronize()
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            fw, bk = [], []
+            for _ in range(2):
+                evs[0].record(stream)
+                ctproj.ctp_project(pv, xv, yv)
+                evs[1].record(stream)
+                ctproj.ctp_backproject(pv, yv, bv)
+                evs[2].record(stream)
+                torch.cuda.synchronize()
+                fw.append(evs[0].elapsed_time(evs[1]))
+                bk.append(evs[1].elapsed_time(evs[2]))
+            vvv = float(gv.n_vox) * gv.n_views
+            out["variants"][name] = {
+                "method": method, "fwd_ms": round(float(np.mean(fw)), 3),
+                "back_ms": round(float(np.mean(bk)), 3),
+                "gups_pair": round(2.0 * vvv / ((np.mean(fw) + np.mean(bk)) * 1e-3) / 1e9, 2)}
+            print(f"[bench] {name}: fwd {np.mean(fw):.2f} ms, back {np.mean(bk):.2f} ms",
+                  file=sys.stderr, flush=True)
+            pv.close()
+            del xv, yv, bv
 
     if not args.no_recon:
         # FDK of the same scan: ramp filter + recon-mode (depth-weighted) back projection

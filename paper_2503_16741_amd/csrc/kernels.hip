@@ -1576,33 +1576,36 @@ struct AmpOp {
 };
 
 // ============================================================================================
-// Ramp filter of filtered back projection: one detector row per work-group.  The row, weighted
-// by the cosine of its rays, and the scaled ramp taps h(n), n = -(nu-1) .. nu-1, sit in LDS;
-// output i is sum_k h(i - k) row[k] (lanes read consecutive taps and the same row element).
+// Ramp filter of filtered back projection.  A work-group filters kRampRows rows of one view.
+// LDS holds the scaled ramp taps h(n), n = -np .. np-1 (np = nu rounded up to 4; taps[n + np]),
+// computed once per work-group, and the current cosine-weighted row (zero past nu).  Each
+// thread computes 4 consecutive outputs: per step of 4 inputs it reads the 4 row values (one
+// broadcast float4) and an aligned window of 8 taps (two float4) and does 16 FMAs.
 // ============================================================================================
-constexpr int kRampThreads = 256;
+constexpr int kRampThreads = 128;
+constexpr int kRampRows = 8;
 
 template <int DET, typename TI, typename TO>
 __global__ __launch_bounds__(kRampThreads) void ramp_kernel(Params P, const ViewRec *__restrict__ views,
                                                             const TI *in, TO *out, int window,
                                                             float dbeta, int two_d)
 {
-    extern __shared__ float sm[];
-    const int nu = P.nu;
-    float *taps = sm;
-    float *row = sm + 2 * nu - 1;
-    const int j = blockIdx.x;            // detector row (3D) or batch item (2D)
+    extern __shared__ float4 sm4[];
+    float *sm = reinterpret_cast<float *>(sm4);
+    const int nu = P.nu, np = (nu + 3) & ~3;
+    float *taps = sm;                    // 2 np
+    float *row = sm + 2 * np;            // np
+    const int rows = two_d ? P.nz : P.nv;
+    const int j0 = blockIdx.x * kRampRows;
     const int view = blockIdx.y;
     const int b = blockIdx.z;            // batch item (3D)
     const ViewRec &V = views[view];
-    const int64_t base = (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
-                         (int64_t)j * P.sino_row_stride;
     const float sdd = V.sdd, sad = V.sad;
     const float a = DET == kFlat ? P.du : P.du / sdd;          // pitch of the ramp samples
     const float scale = DET == kFlat ? dbeta * (sdd / sad) * P.du * 0.5f : dbeta * a / (2.0f * sad);
     const float c0 = 1.0f / (9.8696044010893586f * a * a);    // 1 / (pi a)^2
-    for (int t = threadIdx.x; t < 2 * nu - 1; t += blockDim.x) {
-        const int n = t - (nu - 1);
+    for (int t = threadIdx.x; t < 2 * np; t += blockDim.x) {
+        const int n = t - np;
         const float fn = (float)n;
         float h;
         if (window == 0)
@@ -1617,32 +1620,53 @@ __global__ __launch_bounds__(kRampThreads) void ramp_kernel(Params P, const View
     }
     // (s - d).eu: column position of the source's foot on a flat detector
     const float us = -(V.dms[0] * V.eu[0] + V.dms[1] * V.eu[1] + V.dms[2] * V.eu[2]);
-    const float vz = two_d ? 0.0f : fmaf((float)j + 0.5f, P.dv, V.ve0) - V.sd_ev;
-    for (int k = threadIdx.x; k < nu; k += blockDim.x) {
-        const float u = fmaf((float)k + 0.5f, P.du, V.ue0);
-        float c;
-        if (DET == kFlat) {
-            const float du_ = u - us;
-            c = sdd / sqrtf(fmaf(sdd, sdd, fmaf(du_, du_, vz * vz)));
-        } else {
-            c = cosf(u / sdd) * sdd / sqrtf(fmaf(sdd, sdd, vz * vz));
+    for (int j = j0; j < min(j0 + kRampRows, rows); ++j) {
+        const int64_t base = (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
+                             (int64_t)j * P.sino_row_stride;
+        const float vz = two_d ? 0.0f : fmaf((float)j + 0.5f, P.dv, V.ve0) - V.sd_ev;
+        __syncthreads();                 // the previous row has been consumed
+        for (int k = threadIdx.x; k < np; k += blockDim.x) {
+            float val = 0.0f;
+            if (k < nu) {
+                const float u = fmaf((float)k + 0.5f, P.du, V.ue0);
+                float c;
+                if (DET == kFlat) {
+                    const float du_ = u - us;
+                    c = sdd / sqrtf(fmaf(sdd, sdd, fmaf(du_, du_, vz * vz)));
+                } else {
+                    c = cosf(u / sdd) * sdd / sqrtf(fmaf(sdd, sdd, vz * vz));
+                }
+                val = to_f32(in[base + k]) * c;
+            }
+            row[k] = val;
         }
-        row[k] = to_f32(in[base + k]) * c;
-    }
-    __syncthreads();                     // the whole row is read before any output is written
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
-        const float *h = taps + (i + nu - 1);
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-        int k = 0;
-        for (; k + 3 < nu; k += 4) {
-            s0 = fmaf(h[-k], row[k], s0);
-            s1 = fmaf(h[-k - 1], row[k + 1], s1);
-            s2 = fmaf(h[-k - 2], row[k + 2], s2);
-            s3 = fmaf(h[-k - 3], row[k + 3], s3);
+        __syncthreads();                 // the whole row is read before any output is written
+        for (int i0 = 4 * threadIdx.x; i0 < np; i0 += 4 * blockDim.x) {
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+            // taps[i0 - k0 + np - 4 + m] = h(i0 - k0 - 4 + m): output r, input k0 + kk uses m = r - kk + 4
+            // float4 views keep the 16-byte alignment visible (i0, np, k0 are multiples of 4)
+            const float4 *wb = sm4 + ((i0 + np - 4) >> 2);
+            const float4 *rv = sm4 + ((2 * np) >> 2);
+#pragma unroll 4
+            for (int k4 = 0; k4 < (np >> 2); ++k4) {
+                const float4 x = rv[k4];
+                const float4 e0 = wb[-k4];
+                const float4 e1 = wb[1 - k4];
+                // e0.x is not needed; keeping it live makes the compiler read whole 16-byte
+                // vectors (lanes are 16 bytes apart: 32-bit reads would conflict 8-way)
+                asm volatile("" : : "v"(e0.x));
+                // e0 = (m0, m1, m2, m3), e1 = (m4, m5, m6, m7)
+                s0 = fmaf(e1.x, x.x, s0); s0 = fmaf(e0.w, x.y, s0); s0 = fmaf(e0.z, x.z, s0); s0 = fmaf(e0.y, x.w, s0);
+                s1 = fmaf(e1.y, x.x, s1); s1 = fmaf(e1.x, x.y, s1); s1 = fmaf(e0.w, x.z, s1); s1 = fmaf(e0.z, x.w, s1);
+                s2 = fmaf(e1.z, x.x, s2); s2 = fmaf(e1.y, x.y, s2); s2 = fmaf(e1.x, x.z, s2); s2 = fmaf(e0.w, x.w, s2);
+                s3 = fmaf(e1.w, x.x, s3); s3 = fmaf(e1.z, x.y, s3); s3 = fmaf(e1.y, x.z, s3); s3 = fmaf(e1.x, x.w, s3);
+            }
+            const float sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (i0 + r < nu)
+                    out[base + i0 + r] = from_f32<TO>(sv[r]);
         }
-        for (; k < nu; ++k)
-            s0 = fmaf(h[-k], row[k], s0);
-        out[base + i] = from_f32<TO>((s0 + s1) + (s2 + s3));
     }
 }
 
@@ -1773,8 +1797,9 @@ hipError_t launch_ramp(const Params &p, const LaunchCfg &c, const ViewRec *views
                        float dbeta, hipStream_t st)
 {
     const int two_d = c.geom == kFan2D ? 1 : 0;
-    dim3 grid((unsigned)(two_d ? p.nz : p.nv), (unsigned)p.n_views, (unsigned)batch);
-    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(float);
+    const int rows = two_d ? p.nz : p.nv;
+    dim3 grid((unsigned)((rows + kRampRows - 1) / kRampRows), (unsigned)p.n_views, (unsigned)batch);
+    const size_t lds = (size_t)(3 * ((p.nu + 3) & ~3)) * sizeof(float);
     if (c.det == kCurved)
         return ramp_launch<kCurved>(p, views, in, in_dtype, out, out_dtype, grid, lds, window, dbeta,
                                     two_d, st);
