@@ -493,7 +493,9 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 
 // NC: the column's number of footprint cells in this strip (weights w[0..NC-1]); the emit of
 // row j (j = -1 lands in the guard row below row 0) adds round(row value x w_k) to the NC cells.
-template <int K, int NC, bool NORM>
+// INSIDE: the whole column projects into rows [0, R - 1) (checked per column, uniform), so the
+// row loops need no clamping to the row window.
+template <int K, int NC, bool NORM, bool INSIDE>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
                                            const float (&w)[K], int *accs, int SW, int R,
@@ -523,7 +525,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
             qf[f] = fmaxf(vn, vf);
         }
         // skip runs entirely outside the row window
-        if (qf[nq] < 0.0f || p[0] >= fR)
+        if (!INSIDE && (qf[nq] < 0.0f || p[0] >= fR))
             continue;
         if constexpr (NORM) {
             // recon mode: each voxel's axial trapezoid normalised to unit area
@@ -532,7 +534,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                 if (q < nq)
                     v[q] *= fdiv(2.0f, (p[q + 1] + qf[q + 1]) - (p[q] + qf[q]));
         }
-        int tp = max((int)floorf(p[0]), -1);     // last edge handled (C = 0 at floor(p0))
+        int tp = INSIDE ? (int)floorf(p[0]) : max((int)floorf(p[0]), -1);   // C = 0 at floor(p0)
         // C and the prefix S stay in FP32: a run holds four slices, so they are sums of a few
         // terms and the row differences C(j+1) - C(j) lose at most a few ulps of x.
         float Cprev = 0.0f, S = 0.0f;
@@ -552,7 +554,8 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                 //   v_q (min(t - p, w)^2 / (2w) + max(t - q, 0)) - v_{q-1} max(q - t, 0)^2 / (2w)
                 const float pz = p[q], qz = qf[q], wz = qz - pz;
                 const float h = wz > 1e-12f ? 0.5f * fast_rcp(wz) : 0.0f;
-                const int te = min((int)ceilf(fminf(p[q + 1], fR + 1.0f)) - 1, R);
+                const int te = INSIDE ? (int)ceilf(p[q + 1]) - 1
+                                      : min((int)ceilf(fminf(p[q + 1], fR + 1.0f)) - 1, R);
                 for (int t = tp + 1; t <= te; ++t) {
                     // with u = t - q and e = max(u, 0): min(t - p, w) = (t - p) - e and
                     // max(q - t, 0) = e - u (no min/max of loop-invariant operands)
@@ -572,7 +575,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
         {
             const float pt = p[nq], qt = qf[nq], wt = qt - pt;
             const float h = wt > 1e-12f ? 0.5f * fast_rcp(wt) : 0.0f;
-            const int te = min((int)floorf(fminf(qt, fR)) + 1, R);
+            const int te = INSIDE ? (int)floorf(qt) + 1 : min((int)floorf(fminf(qt, fR)) + 1, R);
             for (int t = tp + 1; t <= te; ++t) {
                 const float d2 = fmaxf(qt - (float)t, 0.0f);
                 emit(t, fmaf(-vm1, d2 * d2 * h, S));
@@ -582,7 +585,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
 }
 
 // Dispatch the SF run on the column's cell count (uniform across the wavefront).
-template <int K, bool NORM>
+template <int K, bool NORM, bool INSIDE>
 __device__ __forceinline__ void sf_fwd_run_nc(const float *__restrict__ colp, int nz, float an,
                                               float bn, float af, float bf,
                                               const float (&w)[K], int nc, int *accs, int SW,
@@ -590,15 +593,15 @@ __device__ __forceinline__ void sf_fwd_run_nc(const float *__restrict__ colp, in
 {
     if constexpr (K <= 4) {
         switch (nc) {
-        case 1: sf_fwd_run<K, 1, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
-        case 2: sf_fwd_run<K, 2, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
-        case 3: sf_fwd_run<K, (K >= 3 ? 3 : K), NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
-        default: sf_fwd_run<K, K, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 1: sf_fwd_run<K, 1, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 2: sf_fwd_run<K, 2, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 3: sf_fwd_run<K, (K >= 3 ? 3 : K), NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        default: sf_fwd_run<K, K, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
         }
     } else {
         // wide footprints: all K cells (weights past nc are zero; the extra cells stay within
         // the strip row plus its padding)
-        sf_fwd_run<K, K, NORM>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane);
+        sf_fwd_run<K, K, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane);
     }
 }
 
@@ -824,8 +827,20 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
                         if (sf_fast_ok(s_an, s_bn, s_af, s_bf, P.nz)) {
-                            sf_fwd_run_nc<K, METHOD == kSFR>(colp, P.nz, s_an, s_bn, s_af, s_bf,
-                                                             sw, s_nc, accs, SW, R, lane);
+                            // faces increase with z (sf_fast_ok): the column spans
+                            // [min(an, af), max of the top face]
+                            const float fnz = (float)P.nz;
+                            const bool inside = fminf(s_an, s_af) >= 0.0f &&
+                                                fmaxf(fmaf(s_bn, fnz, s_an), fmaf(s_bf, fnz, s_af)) <
+                                                    (float)(R - 1);
+                            if (inside)
+                                sf_fwd_run_nc<K, METHOD == kSFR, true>(colp, P.nz, s_an, s_bn, s_af,
+                                                                       s_bf, sw, s_nc, accs, SW, R,
+                                                                       lane);
+                            else
+                                sf_fwd_run_nc<K, METHOD == kSFR, false>(colp, P.nz, s_an, s_bn, s_af,
+                                                                        s_bf, sw, s_nc, accs, SW, R,
+                                                                        lane);
                             continue;
                         }
                     }
