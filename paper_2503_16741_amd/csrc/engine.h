@@ -24,7 +24,10 @@ enum Det : int { kFlat = 0, kCurved = 1 };
 // back projection of FBP / FDK and its transpose).
 enum Method : int { kSF = 0, kDD = 1, kSFR = 2 };
 
-constexpr int kStripW = 16;      // detector columns owned by one forward work-group
+#ifndef CTP_STRIPW
+#define CTP_STRIPW 16
+#endif
+constexpr int kStripW = CTP_STRIPW;  // detector columns owned by one forward work-group
 constexpr int kMaxCells = 16;    // widest supported transaxial footprint (columns)
 constexpr int kRowsMax = 512;    // detector rows (or 2D batch items) held in LDS at once
 #ifndef CTP_ZCHUNK

@@ -394,11 +394,22 @@ __device__ __forceinline__ void sf_voxel_noncirc(const ViewRec &V, const Params 
     const float dW[4] = {-wx - wy, wx - wy, -wx + wy, wx + wy};
     const float iWc = fast_rcp(Wc);
     const float uc = fmaf(V.Du * ac, iWc, V.cu);
-    float t[4];
+    // per transaxial corner k: depths at the mid-plane (Wk), bottom (Wb) and top (Wt) corners;
+    // their three reciprocals come from one reciprocal of the product
+    const float hc = fmaf(xc, V.ev[0], fmaf(yc, V.ev[1], fmaf(zc, V.ev[2], -V.sev)));
+    const float ex = hx * V.ev[0], ey = hy * V.ev[1], ez = hz * V.ev[2];
+    const float nzh = hz * V.n[2];
+    const float dh[4] = {-ex - ey, ex - ey, -ex + ey, ex + ey};
+    float t[4], vb[4], vt[4];
+    const float cvr = V.cv - row0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float Wk = Wc + dW[k];
-        t[k] = V.Du * fmaf(da[k], Wc, -ac * dW[k]) * fast_rcp(Wk * Wc);
+        const float Wk = Wc + dW[k], Wb = Wk + nzh, Wt = Wk - nzh;
+        const float bt = Wb * Wt, r3 = fast_rcp(bt * Wk);
+        const float iWk = bt * r3, iWb = (Wt * Wk) * r3, iWt = (Wb * Wk) * r3;
+        t[k] = V.Du * fmaf(da[k], Wc, -ac * dW[k]) * (iWk * iWc);
+        vb[k] = fmaf(V.Dv * (hc + dh[k] - ez), iWb, cvr);
+        vt[k] = fmaf(V.Dv * (hc + dh[k] + ez), iWt, cvr);
     }
     const float of = floorf(fminf(fmaxf(uc, -1.0e7f), 1.0e7f)), base = uc - of;
     r.o = (int)of;
@@ -408,22 +419,13 @@ __device__ __forceinline__ void sf_voxel_noncirc(const ViewRec &V, const Params 
     r.t3 = t[3] + base;
     sort4(r.t0, r.t1, r.t2, r.t3);
     // axial: v of the four bottom and four top corners
-    const float hc = fmaf(xc, V.ev[0], fmaf(yc, V.ev[1], fmaf(zc, V.ev[2], -V.sev)));
-    const float ex = hx * V.ev[0], ey = hy * V.ev[1], ez = hz * V.ev[2];
-    const float nzh = hz * V.n[2];
-    const float dh[4] = {-ex - ey, ex - ey, -ex + ey, ex + ey};
     float bmn = 3.0e38f, bmx = -3.0e38f, tmn = 3.0e38f, tmx = -3.0e38f;
-    const float cvr = V.cv - row0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float hb = hc + dh[k] - ez, ht = hc + dh[k] + ez;
-        const float Wb = Wc + dW[k] + nzh, Wt = Wc + dW[k] - nzh;
-        const float vb = fmaf(V.Dv * hb, fast_rcp(Wb), cvr);
-        const float vt = fmaf(V.Dv * ht, fast_rcp(Wt), cvr);
-        bmn = fminf(bmn, vb);
-        bmx = fmaxf(bmx, vb);
-        tmn = fminf(tmn, vt);
-        tmx = fmaxf(tmx, vt);
+        bmn = fminf(bmn, vb[k]);
+        bmx = fmaxf(bmx, vb[k]);
+        tmn = fminf(tmn, vt[k]);
+        tmx = fmaxf(tmx, vt[k]);
     }
     float k0 = bmn, k1 = bmx, k2 = tmn, k3 = tmx;
     sort4(k0, k1, k2, k3);

@@ -143,3 +143,13 @@ def test_projector_module_arguments():
         Projector(g, "proj", "SF", "sideways")
     p = Projector(g, "proj", "dd", "backward")
     assert p.method == "dd" and p.direction == "backward"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message before touching a device."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
