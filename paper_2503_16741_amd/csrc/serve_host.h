@@ -12,8 +12,12 @@
 
 namespace ctp {
 
-// First-fit allocator over [0, size) in 256-byte units.  Offsets only: the caller adds them to
-// the base of its device arena.  Free blocks are coalesced with their neighbours.
+// Allocator over [0, size) in 256-byte units with two ends: `alloc` places a block first-fit
+// from the bottom, `alloc_high` last-fit from the top (at the end of the highest free block
+// that holds it).  The serving engine keeps long-lived outputs at the bottom and the scratch of
+// running calls at the top, so freed scratch always rejoins the free space above the outputs
+// instead of leaving holes between them.  Offsets only: the caller adds them to the base of its
+// device arena.  Free blocks are coalesced with their neighbours.
 class Arena {
 public:
     static constexpr size_t kAlign = 256;
@@ -45,6 +49,30 @@ public:
             free_.erase(it);
             if (rest > 0)
                 free_[off + n] = rest;
+            used_[off] = n;
+            in_use_ += n;
+            if (in_use_ > peak_)
+                peak_ = in_use_;
+            return off;
+        }
+        return kFail;
+    }
+
+    // Highest-address placement: the top end of the highest free block that holds `bytes`.
+    size_t alloc_high(size_t bytes)
+    {
+        const size_t n = round_up(bytes == 0 ? 1 : bytes);
+        if (n < bytes)
+            return kFail;   // overflow
+        for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
+            if (it->second < n)
+                continue;
+            const size_t start = it->first, rest = it->second - n;
+            const size_t off = start + rest;
+            if (rest > 0)
+                it->second = rest;
+            else
+                free_.erase(std::next(it).base());
             used_[off] = n;
             in_use_ += n;
             if (in_use_ > peak_)

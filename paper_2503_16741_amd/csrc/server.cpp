@@ -196,7 +196,8 @@ struct ctp_server {
                 continue;
             size_t scratch_off = ctp::Arena::kFail;
             if (staging + ws > 0) {
-                scratch_off = alloc.alloc(staging + ws);
+                // scratch lives only while the call runs: take it from the top of the arena
+                scratch_off = alloc.alloc_high(staging + ws);
                 if (scratch_off == ctp::Arena::kFail) {
                     alloc.release(out_off);
                     continue;

@@ -32,16 +32,32 @@ static void allocator_model_test(unsigned seed)
         if (live.empty() || rng() % 100 < 55) {
             const size_t bytes = rng() % 9 == 0 ? 0 : 1 + rng() % (Arena::kAlign * 20);
             const size_t n = bytes == 0 ? 1 : (bytes + Arena::kAlign - 1) / Arena::kAlign;
-            // first fit in the model
+            const bool high = rng() % 2 == 0;
             size_t want = Arena::kFail;
-            for (size_t u = 0; u + n <= units && want == Arena::kFail; ++u) {
-                bool fr = true;
-                for (size_t k = 0; k < n && fr; ++k)
-                    fr = owner[u + k] < 0;
-                if (fr)
-                    want = u * Arena::kAlign;
+            if (!high) {
+                // first fit in the model
+                for (size_t u = 0; u + n <= units && want == Arena::kFail; ++u) {
+                    bool fr = true;
+                    for (size_t k = 0; k < n && fr; ++k)
+                        fr = owner[u + k] < 0;
+                    if (fr)
+                        want = u * Arena::kAlign;
+                }
+            } else {
+                // the top end of the highest free run that holds n units
+                size_t end = units;
+                while (end > 0 && want == Arena::kFail) {
+                    while (end > 0 && owner[end - 1] >= 0)
+                        --end;
+                    size_t beg = end;
+                    while (beg > 0 && owner[beg - 1] < 0)
+                        --beg;
+                    if (end - beg >= n)
+                        want = (end - n) * Arena::kAlign;
+                    end = beg;
+                }
             }
-            const size_t off = a.alloc(bytes);
+            const size_t off = high ? a.alloc_high(bytes) : a.alloc(bytes);
             CHECK(off == want);
             if (off != Arena::kFail) {
                 CHECK(off % Arena::kAlign == 0);
@@ -114,6 +130,9 @@ int main()
     a.reset(1024);
     CHECK(a.alloc(SIZE_MAX - 10) == Arena::kFail);       // size overflow
     CHECK(a.alloc(1024) == 0 && a.alloc(1) == Arena::kFail);
+    a.reset(4096);
+    CHECK(a.alloc_high(300) == 4096 - 512 && a.alloc(1) == 0 && a.alloc_high(256) == 4096 - 768);
+    CHECK(a.alloc_high(SIZE_MAX - 10) == Arena::kFail);
     batch_candidates_test();
     std::printf("ok\n");
     return 0;

@@ -1,0 +1,239 @@
+// CPU simulation of the serving engine: csrc/server.cpp compiled unchanged against a simulated
+// device (tests/host/fakehip) on which every stream runs its work for a set duration of wall
+// time, events complete when the work before them has run, and the projector calls are stubs
+// that only check their workspace against the library's size formulas and occupy their stream.
+// Scenarios: bursts of mixed requests (large calls first, then many small ones of several
+// plans, directions and storage types) with outputs held until every request is done, as a
+// client that reads its results in submission order would; every request must complete.
+// Prints "ok" and exits 0 on success.
+#include "../../paper_2503_16741_amd/csrc/server.cpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+
+// ---- simulated device -------------------------------------------------------------------------
+struct SimStream {
+    std::mutex mu;
+    double busy_until = 0.0;     // microseconds on the steady clock
+};
+struct SimEvent {
+    std::atomic<double> ready_at{0.0};
+};
+
+static double now_us()
+{
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+static double enqueue(hipStream_t s, double dur)
+{
+    if (s == nullptr)
+        return now_us() + dur;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->busy_until = std::max(s->busy_until, now_us()) + dur;
+    return s->busy_until;
+}
+
+hipError_t hipGetDevice(int *dev) { *dev = 0; return hipSuccess; }
+hipError_t hipSetDevice(int) { return hipSuccess; }
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = new SimStream(); return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) { delete s; return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t s)
+{
+    const double t = enqueue(s, 0.0);
+    while (now_us() < t)
+        std::this_thread::yield();
+    return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->busy_until = std::max(s->busy_until, e->ready_at.load());
+    return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { *e = new SimEvent(); return hipSuccess; }
+hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) { e->ready_at = enqueue(s, 0.0); return hipSuccess; }
+hipError_t hipEventQuery(hipEvent_t e) { return now_us() >= e->ready_at ? hipSuccess : hipErrorNotReady; }
+hipError_t hipEventSynchronize(hipEvent_t e)
+{
+    while (hipEventQuery(e) != hipSuccess)
+        std::this_thread::yield();
+    return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void *, const void *, size_t n, hipMemcpyKind, hipStream_t s)
+{
+    enqueue(s, 1.0 + n * 1e-6);
+    return hipSuccess;
+}
+hipError_t hipDeviceSynchronize(void) { return hipSuccess; }
+const char *hipGetErrorString(hipError_t e) { return e == hipSuccess ? "success" : "error"; }
+
+// ---- simulated plans: the library's size formulas ---------------------------------------------
+struct ctp_plan {
+    int device = 0;
+    bool two_d = false, recon = false, sf = true;
+    size_t nvox = 0, ncell = 0, plane = 0;
+    double us_per_item = 10.0;
+};
+
+static size_t a256(size_t n) { return (n + 255) & ~(size_t)255; }
+static size_t esz(ctp_dtype d) { return d == CTP_F32 ? 4 : 2; }
+
+static thread_local std::string sim_err;
+namespace ctp {
+ctp_status set_error(ctp_status st, const std::string &msg) { sim_err = msg; return st; }
+void clear_error() { sim_err.clear(); }
+int plan_device(const ctp_plan *plan) { return plan->device; }
+}  // namespace ctp
+extern "C" const char *ctp_last_error(void) { return sim_err.c_str(); }
+
+extern "C" ctp_status ctp_plan_bytes(const ctp_plan *p, ctp_dtype d, int64_t batch, size_t *vb,
+                                     size_t *sb)
+{
+    if (vb)
+        *vb = p->nvox * (size_t)batch * esz(d);
+    if (sb)
+        *sb = p->ncell * (size_t)batch * esz(d);
+    return CTP_OK;
+}
+
+extern "C" ctp_status ctp_workspace_bytes(const ctp_plan *p, ctp_direction dir, ctp_dtype vd,
+                                          ctp_dtype sd, int64_t batch, size_t *bytes)
+{
+    const size_t b = (size_t)batch;
+    if (dir == CTP_FORWARD) {
+        const size_t item = p->two_d ? p->plane : p->nvox;
+        const size_t bpi = std::max<size_t>(1, std::min<size_t>((item + 8191) / 8192, 1024));
+        size_t t = a256(8 * b) + a256(b * bpi * 4) + a256(b * p->nvox * 4);
+        if (sd != CTP_F32)
+            t += p->ncell * b * 4;
+        *bytes = t;
+    } else {
+        const bool scaled = !(sd == CTP_F32 && (p->recon || (p->two_d && p->sf)));
+        const size_t off = scaled ? a256(p->ncell * b * 4) : 0;
+        *bytes = off + (vd == CTP_F32 ? 0 : p->nvox * b * 4);
+    }
+    return CTP_OK;
+}
+
+static std::atomic<int> bad_calls{0};
+
+static ctp_status sim_call(const ctp_plan *p, ctp_direction dir, ctp_dtype vd, ctp_dtype sd,
+                           int64_t batch, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    size_t need = 0;
+    ctp_workspace_bytes(p, dir, vd, sd, batch, &need);
+    if (need > 0 && (ws == nullptr || ws_bytes < need || ((uintptr_t)ws & 255u))) {
+        ++bad_calls;
+        return ctp::set_error(CTP_EINVAL, "workspace too small or misaligned");
+    }
+    enqueue(st, p->us_per_item * (double)batch);
+    return CTP_OK;
+}
+
+extern "C" ctp_status ctp_project(const ctp_plan *p, const void *, ctp_dtype vd, void *, ctp_dtype sd,
+                                  int64_t batch, int, void *ws, size_t wsb, hipStream_t st)
+{
+    return sim_call(p, CTP_FORWARD, vd, sd, batch, ws, wsb, st);
+}
+
+extern "C" ctp_status ctp_backproject(const ctp_plan *p, const void *, ctp_dtype sd, void *, ctp_dtype vd,
+                                      int64_t batch, int, void *ws, size_t wsb, hipStream_t st)
+{
+    return sim_call(p, CTP_BACKWARD, vd, sd, batch, ws, wsb, st);
+}
+
+#define CHECK(c)                                                                          \
+    do {                                                                                  \
+        if (!(c)) {                                                                       \
+            std::fprintf(stderr, "%s:%d: CHECK(%s) failed\n", __FILE__, __LINE__, #c);    \
+            std::exit(1);                                                                 \
+        }                                                                                 \
+    } while (0)
+
+struct Req {
+    ctp_plan *plan;
+    ctp_direction dir;
+    ctp_dtype in, out;
+};
+
+// One burst: n_big large forward calls, then n_small mixed requests; the client waits for every
+// ticket in order and releases the outputs only at the end.
+static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, int n_big,
+                  int n_small)
+{
+    ctp_plan big, fan, cone, recon;
+    big.nvox = 128ull * 128 * 128; big.ncell = 300ull * 200 * 256; big.us_per_item = 1500;
+    fan.two_d = true; fan.nvox = fan.plane = 40 * 36; fan.ncell = 24 * 96; fan.us_per_item = 40;
+    cone.nvox = 28 * 26 * 18; cone.ncell = 20 * 40 * 64; cone.us_per_item = 60;
+    recon = cone; recon.recon = true;
+    ctp_plan *smalls[3] = {&fan, &cone, &recon};
+    std::mt19937 rng(seed);
+    std::vector<Req> reqs;
+    for (int i = 0; i < n_big; ++i)
+        reqs.push_back({&big, CTP_FORWARD, CTP_F32, CTP_F32});
+    const ctp_dtype dts[3] = {CTP_F32, CTP_BF16, CTP_F16};
+    for (int i = 0; i < n_small; ++i) {
+        Req r;
+        r.plan = smalls[rng() % 3];
+        r.dir = rng() % 2 ? CTP_FORWARD : CTP_BACKWARD;
+        r.in = dts[rng() % 3];
+        r.out = rng() % 10 < 7 ? r.in : CTP_F32;
+        reqs.push_back(r);
+    }
+    ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch};
+    ctp_server *srv = nullptr;
+    CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
+    static char dummy_input[16];
+    std::vector<uint64_t> tickets;
+    for (const Req &r : reqs) {
+        uint64_t t = 0;
+        const ctp_status st = ctp_server_submit(srv, r.plan, r.dir, dummy_input, r.in, r.out,
+                                                nullptr, &t);
+        CHECK(st == CTP_OK);
+        tickets.push_back(t);
+    }
+    for (size_t i = 0; i < tickets.size(); ++i) {
+        void *res = nullptr;
+        const ctp_status st = ctp_server_wait(srv, tickets[i], 20 * 1000 * 1000, &res);
+        if (st != CTP_OK) {
+            ctp_server_stats s{};
+            ctp_server_get_stats(srv, &s);
+            std::fprintf(stderr,
+                         "seed %u arena %zu slots %d max_batch %d: request %zu of %zu: %s "
+                         "(status %d); submitted %lld completed %lld failed %lld calls %lld\n",
+                         seed, arena_bytes, slots, max_batch, i, tickets.size(), ctp_last_error(),
+                         (int)st, (long long)s.submitted, (long long)s.completed,
+                         (long long)s.failed, (long long)s.calls);
+            std::exit(1);
+        }
+        CHECK(res != nullptr);
+    }
+    for (uint64_t t : tickets)
+        CHECK(ctp_server_release(srv, t, nullptr) == CTP_OK);
+    ctp_server_stats s{};
+    ctp_server_get_stats(srv, &s);
+    CHECK(s.completed == (int64_t)tickets.size() && s.failed == 0);
+    CHECK(s.arena_peak <= arena_bytes);
+    CHECK(ctp_server_destroy(srv) == CTP_OK);
+}
+
+int main()
+{
+    // the configuration of the GPU serving test, then tighter arenas and other slot counts
+    for (unsigned seed = 1; seed <= 12; ++seed)
+        burst(seed, 256u << 20, 2, 6, 4, 60);
+    for (unsigned seed = 1; seed <= 6; ++seed) {
+        burst(100 + seed, 200u << 20, 2, 6, 3, 60);
+        burst(200 + seed, 256u << 20, 4, 8, 4, 60);
+        burst(300 + seed, 64u << 20, 3, 4, 0, 200);
+    }
+    CHECK(bad_calls == 0);
+    std::printf("ok\n");
+    return 0;
+}

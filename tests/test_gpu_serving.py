@@ -40,7 +40,13 @@ def geometries():
                          dz=0.5, nu=256, nv=200, du=0.5, dv=0.5, n_views=300,
                          theta=synth.full_circle(300), sad=300.0, sdd=500.0)
     return {"fan": (fan, "sf"), "fan_dd": (fan, "dd"), "flat": (flat, "sf"),
-            "curved_dd": (curved, "dd"), "noncirc": (noncirc, "sf"), "big": (big, "sf")}
+            "curved_dd": (curved, "dd"), "noncirc": (noncirc, "sf"), "big": (big, "sf"),
+            "curved_recon": (curved, "sf", "recon")}
+
+
+def make_plan(ctproj, entry):
+    g, m = entry[0], entry[1]
+    return ctproj.ctp_plan_create(g, m, entry[2] if len(entry) > 2 else "proj")
 
 
 def alone(ctproj, plan, direction, x, out_dtype):
@@ -58,7 +64,7 @@ def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc):
     torch = torch_gpu
     from paper_2503_16741_amd import ctproj
     geo = geometries()
-    plans = {k: ctproj.ctp_plan_create(g, m) for k, (g, m) in geo.items()}
+    plans = {k: make_plan(ctproj, e) for k, e in geo.items()}
     srv = ctproj.Server(256 << 20, n_slots=2, max_batch=6)
     rng = np.random.default_rng(42)
     reqs = []
@@ -66,11 +72,12 @@ def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc):
     # gets merged
     for i in range(4):
         reqs.append(("big", "forward", torch.float32, torch.float32, 1000 + i))
-    kinds = ["fan", "fan_dd", "flat", "curved_dd", "noncirc"]
+    kinds = ["fan", "fan_dd", "flat", "curved_dd", "noncirc", "curved_recon"]
     for i in range(60):
         k = kinds[int(rng.integers(len(kinds)))]
         d = "forward" if rng.random() < 0.5 else "backward"
-        dt = torch.float32 if rng.random() < 0.6 else torch.bfloat16
+        u = rng.random()
+        dt = torch.float32 if u < 0.5 else torch.bfloat16 if u < 0.8 else torch.float16
         odt = dt if rng.random() < 0.7 else torch.float32
         reqs.append((k, d, dt, odt, i))
     inputs = [make_input(torch, geo[k][0], d, dt, seed) for (k, d, dt, odt, seed) in reqs]
@@ -105,12 +112,14 @@ def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc):
         if k == "big" or dt != torch.float32 or odt != torch.float32 or (k, d) in seen:
             continue
         seen.add((k, d))
-        g, m = geo[k]
+        g, m = geo[k][0], geo[k][1]
+        mode = geo[k][2] if len(geo[k]) > 2 else "proj"
         xin = x.cpu().numpy()
-        ref = orc.forward(g, xin, method=m) if d == "forward" else orc.adjoint(g, xin, method=m)
+        ref = (orc.forward(g, xin, method=m, mode=mode) if d == "forward"
+               else orc.adjoint(g, xin, method=m, mode=mode))
         err = float(np.max(np.abs(y.cpu().numpy() - ref)) / max(np.max(np.abs(ref)), 1e-30))
         assert err <= TOL, (k, d, err)
-    assert len(seen) >= 6
+    assert len(seen) >= 7
     srv.close()
 
 
@@ -119,7 +128,7 @@ def test_admission_waits_for_memory(torch_gpu):
     released; a request that can never fit is refused at submission."""
     torch = torch_gpu
     from paper_2503_16741_amd import ctproj
-    g, m = geometries()["flat"]
+    g, m = geometries()["flat"][:2]
     plan = ctproj.ctp_plan_create(g, m)
     vb, sb = ctproj.ctp_plan_bytes(plan, 1)
     ws = ctproj.ctp_workspace_bytes(plan, ctproj.CTP_FORWARD, 1)
@@ -161,7 +170,7 @@ def test_results_stay_resident(torch_gpu):
     """Outputs keep their values while later requests run, until released."""
     torch = torch_gpu
     from paper_2503_16741_amd import ctproj
-    g, m = geometries()["fan"]
+    g, m = geometries()["fan"][:2]
     plan = ctproj.ctp_plan_create(g, m)
     srv = ctproj.Server(64 << 20, n_slots=3, max_batch=8)
     x0 = make_input(torch, g, "forward", torch.float32, 3)

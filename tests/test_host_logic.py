@@ -28,6 +28,20 @@ def test_serve_host_allocator_and_batching(tmp_path):
     assert res.returncode == 0 and res.stdout.strip() == "ok", res.stdout + res.stderr
 
 
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_serving_engine_simulated_device(tmp_path):
+    """csrc/server.cpp compiled unchanged against a simulated device (streams with timed work,
+    events, stub projector calls with the library's workspace formulas): bursts of mixed
+    requests whose outputs the client holds until all are done must all complete, with every
+    call given a large enough workspace.  A scratch block placed between outputs used to leave
+    a request that could never be admitted (fragmentation); scratch now comes from the top."""
+    exe = _cc(tmp_path, os.path.join(ROOT, "tests", "host", "serve_sim.cpp"), "sim",
+              ["g++", "-std=c++17", "-O1", "-pthread", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=all", "-I" + os.path.join(ROOT, "tests", "host", "fakehip")])
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0 and res.stdout.strip() == "ok", res.stdout + res.stderr
+
+
 PROBE = r"""
 #include <stdio.h>
 #include <stddef.h>
