@@ -5,10 +5,12 @@
  * (ctproj.h) as they arrive, and runs them on one device while others are still running:
  *
  *   - Memory.  The caller hands the server one device arena (its HBM budget).  Every admitted
- *     call takes from it the outputs of its requests, the workspace of the call
- *     (ctp_workspace_bytes) and, when several requests are merged, a staging copy of their
- *     inputs.  A request is admitted only when that footprint fits in the free arena; until
- *     then it waits in the queue.  Outputs stay resident in the arena until released.
+ *     call takes from it the outputs of its requests (one block, placed from the bottom of the
+ *     arena) and its scratch -- the workspace of the call (ctp_workspace_bytes) and, when
+ *     several requests are merged, a staging copy of their inputs (one block, placed from the
+ *     top, freed when the call completes).  A request is admitted only when those blocks fit;
+ *     until then it waits in the queue.  Outputs stay resident in the arena until released, so
+ *     a client that holds results can keep later requests waiting (a wait then times out).
  *   - Batching.  When a slot is free the oldest queued request is admitted together with the
  *     later queued requests that share its plan, direction and storage types (at most
  *     max_batch; the paper's batched, channelled tensors, Section 1 and 2.4: one plan serves the

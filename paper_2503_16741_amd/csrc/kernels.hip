@@ -691,7 +691,10 @@ __device__ __forceinline__ void fan2d_lane_scatter(const float *__restrict__ col
 // ============================================================================================
 // Forward projector
 // ============================================================================================
-constexpr int kFwdThreads = 512;
+#ifndef CTP_FWD_THREADS
+#define CTP_FWD_THREADS 512
+#endif
+constexpr int kFwdThreads = CTP_FWD_THREADS;
 constexpr int kFwdWaves = kFwdThreads / 64;
 
 template <int GEOM, int DET, int METHOD, int K>

@@ -238,7 +238,9 @@ def _stream_handle(stream) -> int:
 def _workspace(plan: Plan, direction: int, batch: int, device, vol_dtype=CTP_F32,
                sino_dtype=CTP_F32):
     """A cached, 256-byte-aligned workspace tensor for this plan/direction/batch (torch
-    allocations are 512-byte aligned)."""
+    allocations are 512-byte aligned).  One cache entry per plan, direction and device: calls
+    that use the default workspace of the same plan must not run concurrently on different
+    streams (pass ``workspace=`` for that)."""
     import torch
     need = ctp_workspace_bytes(plan, direction, batch, vol_dtype, sino_dtype)
     if need == 0:
@@ -363,7 +365,9 @@ class Server:
 
     ``submit`` queues a request and returns its ticket; ``wait`` returns the output as a tensor
     view into the arena (valid until ``release``).  The input tensor is kept referenced until its
-    request has finished.
+    request has finished.  Outputs hold arena memory until released: a client that keeps every
+    result can make later requests wait for memory that never frees (``wait`` then times out);
+    admission needs one contiguous block per call.
     """
 
     def __init__(self, arena_bytes: int, n_slots: int = 4, max_batch: int = 16, device=None):
