@@ -816,6 +816,18 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                 }
                 const float an = fmaf(col.An, zb0, V.cv - (float)r0), bn = col.An * P.dz;
                 const float af = fmaf(col.Af, zb0, V.cv - (float)r0), bf = col.Af * P.dz;
+                // each lane tests its own column for the run path (faces disjoint and
+                // increasing; inside: the whole column projects into rows [0, R - 1)); the
+                // broadcast loop below reads the answers from two masks
+                uint64_t m_fast = 0, m_inside = 0;
+                if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
+                    const bool fast = nc > 0 && sf_fast_ok(an, bn, af, bf, P.nz);
+                    const float fnz = (float)P.nz;
+                    const bool inside = fast && fminf(an, af) >= 0.0f &&
+                                        fmaxf(fmaf(bn, fnz, an), fmaf(bf, fnz, af)) < (float)(R - 1);
+                    m_fast = __ballot(fast);
+                    m_inside = __ballot(inside);
+                }
                 uint64_t m = __ballot(nc > 0);
                 while (m) {
                     const int c = __ffsll((unsigned long long)m) - 1;
@@ -831,14 +843,8 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
-                        if (sf_fast_ok(s_an, s_bn, s_af, s_bf, P.nz)) {
-                            // faces increase with z (sf_fast_ok): the column spans
-                            // [min(an, af), max of the top face]
-                            const float fnz = (float)P.nz;
-                            const bool inside = fminf(s_an, s_af) >= 0.0f &&
-                                                fmaxf(fmaf(s_bn, fnz, s_an), fmaf(s_bf, fnz, s_af)) <
-                                                    (float)(R - 1);
-                            if (inside)
+                        if ((m_fast >> c) & 1ull) {
+                            if ((m_inside >> c) & 1ull)
                                 sf_fwd_run_nc<K, METHOD == kSFR, true>(colp, P.nz, s_an, s_bn, s_af,
                                                                        s_bf, sw, s_nc, accs, SW, R,
                                                                        lane);
