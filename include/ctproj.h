@@ -142,8 +142,9 @@ ctp_status ctp_workspace_bytes(const ctp_plan *plan, ctp_direction dir, ctp_dtyp
  * set per batch item from that item's max |vol| (relative resolution ~1e-9 of the largest
  * possible cell sum; items with max |vol| * footprint bound below ~2^-96 lose resolution).  An
  * item's result therefore does not depend on the other items of the batch.
- * Errors: CTP_EINVAL (NULL pointers, batch < 1, unknown dtype, workspace too small or
- * misaligned, plan used on another device), CTP_EDEVICE (launch).
+ * Errors: CTP_EINVAL (NULL pointers, batch < 1 or too large -- 2D: more than 2^20 images,
+ * 3D: batch x ceil(nv / 512) above 65535 -- unknown dtype, workspace too small or misaligned,
+ * plan used on another device), CTP_EDEVICE (launch).
  */
 ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype,
                        void *sino, ctp_dtype sino_dtype, int64_t batch, int accumulate,

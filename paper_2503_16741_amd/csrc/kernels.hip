@@ -1471,21 +1471,26 @@ __global__ __launch_bounds__(256) void transpose_zfast_kernel(const T *__restric
     }
 }
 
+// One work-group row per sinogram row (row, view, batch item), grid-strided over all rows so
+// that any batch fits the grid limits.
 template <int GEOM, int DET, int METHOD, typename T>
 __global__ __launch_bounds__(256) void amp_scale_kernel(Params P, const ViewRec *__restrict__ views,
                                                         const T *__restrict__ in,
-                                                        float *__restrict__ out, int nrows)
+                                                        float *__restrict__ out, int nrows,
+                                                        int64_t total_rows)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    const int row = blockIdx.y;
-    const int view = blockIdx.z % P.n_views;
-    const int b = blockIdx.z / P.n_views;
     if (i >= P.nu)
         return;
-    const int64_t idx = (int64_t)b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
-                        (int64_t)row * P.sino_row_stride + i;
-    out[idx] = to_f32(in[idx]) * cell_amp<GEOM, DET, METHOD>(views[view], P, i, row);
-    (void)nrows;
+    for (int64_t r = blockIdx.y; r < total_rows; r += gridDim.y) {
+        const int row = (int)(r % nrows);
+        const int64_t vb = r / nrows;
+        const int view = (int)(vb % P.n_views);
+        const int64_t b = vb / P.n_views;
+        const int64_t idx = b * P.sino_b_stride + (int64_t)view * P.sino_view_stride +
+                            (int64_t)row * P.sino_row_stride + i;
+        out[idx] = to_f32(in[idx]) * cell_amp<GEOM, DET, METHOD>(views[view], P, i, row);
+    }
 }
 
 // ---- dispatch --------------------------------------------------------------------------------
@@ -1525,16 +1530,17 @@ hipError_t amp_launch(const Params &p, const ViewRec *views, const void *in, int
                       float *out, int64_t batch, hipStream_t st)
 {
     const int nrows = GEOM == kFan2D ? p.nz : p.nv;
-    dim3 grid((p.nu + 255) / 256, nrows, (unsigned)(p.n_views * (GEOM == kFan2D ? 1 : batch)));
+    const int64_t total_rows = (int64_t)nrows * p.n_views * (GEOM == kFan2D ? 1 : batch);
+    dim3 grid((p.nu + 255) / 256, (unsigned)std::min<int64_t>(total_rows, 65535), 1);
     if (dtype == 1)
         hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD, __hip_bfloat16>), grid, dim3(256), 0,
-                           st, p, views, (const __hip_bfloat16 *)in, out, nrows);
+                           st, p, views, (const __hip_bfloat16 *)in, out, nrows, total_rows);
     else if (dtype == 2)
         hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD, __half>), grid, dim3(256), 0, st, p,
-                           views, (const __half *)in, out, nrows);
+                           views, (const __half *)in, out, nrows, total_rows);
     else
         hipLaunchKernelGGL((amp_scale_kernel<GEOM, DET, METHOD, float>), grid, dim3(256), 0, st, p,
-                           views, (const float *)in, out, nrows);
+                           views, (const float *)in, out, nrows, total_rows);
     return hipGetLastError();
 }
 

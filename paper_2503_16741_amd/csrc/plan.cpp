@@ -481,8 +481,8 @@ ctp_status prepare_call(const ctp_plan *plan, const void *a, const void *b, ctp_
         if (d != CTP_F32 && d != CTP_BF16 && d != CTP_F16)
             return fail(CTP_EINVAL, "unknown dtype");
     const bool two_d = plan->g.kind == CTP_FAN2D;
-    if (two_d && batch > (int64_t)1 << 24)
-        return fail(CTP_EINVAL, "2D batch too large");
+    if (two_d && batch > (int64_t)1 << 20)
+        return fail(CTP_EINVAL, "2D batch too large (at most 2^20 images)");
     if (!two_d && batch * plan->cfg.n_row_chunks > 65535)
         return fail(CTP_EINVAL, "batch too large");
     size_t need = 0;

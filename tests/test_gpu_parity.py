@@ -166,6 +166,33 @@ def test_2d_large_batch_row_chunks(torch_gpu, orc):
         assert rel_err(xb[b], orc.adjoint(g, s[b])) <= TOL
 
 
+def test_2d_batch_beyond_grid_rows(torch_gpu, orc):
+    """A 2D batch of 70 000 images (more sinogram rows than one grid dimension holds): DD forward
+    and adjoint (the adjoint's amplitude pass strides over the rows) and the ramp filter."""
+    torch = torch_gpu
+    from paper_2503_16741_amd import ctproj
+    from oracle.ramp import ramp_filter
+    g = synth.Geometry(kind="fan2d", det="flat", nx=12, ny=10, nz=1, dx=1.0, dy=1.0, dz=1.0,
+                       nu=24, nv=1, du=1.5, dv=1.0, n_views=3, theta=synth.full_circle(3),
+                       sad=100.0, sdd=200.0)
+    plan = ctproj.ctp_plan_create(g, "dd")
+    B = 70000
+    x = synth.random_volume(g, seed=40, batch=B)
+    y = run_fwd(torch_gpu, plan, x)
+    s = synth.random_sinogram(g, seed=41, batch=B)
+    xb = run_bwd(torch_gpu, plan, s)
+    for b in (0, 65534, 65535, 69999):
+        assert rel_err(y[b], orc.forward(g, x[b], method="dd")) <= TOL, b
+        assert rel_err(xb[b], orc.adjoint(g, s[b], method="dd")) <= TOL, b
+    st = torch.from_numpy(s).cuda()
+    q = torch.empty_like(st)
+    ctproj.ctp_ramp_filter(plan, st, q)
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    for b in (0, 65535, 69999):
+        assert rel_err(qn[b], ramp_filter(g, s[b])) <= TOL, b
+
+
 def test_3d_many_rows(torch_gpu, orc):
     """More detector rows than one LDS row chunk."""
     from paper_2503_16741_amd import ctproj
