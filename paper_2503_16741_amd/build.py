@@ -13,6 +13,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # the kernels never depend on the sign of a zero (lets x + 0 and x * 0 fold)
     "-fno-signed-zeros",
+    # device code never depends on NaN semantics (lets min / max skip canonicalising inputs);
+    # host code keeps them (plan validation tests for non-finite geometry)
+    "-Xarch_device", "-fno-honor-nans",
     # keep hipcc from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",

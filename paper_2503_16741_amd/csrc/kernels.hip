@@ -497,13 +497,16 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 // row j (j = -1 lands in the guard row below row 0) adds round(row value x w_k) to the NC cells.
 // INSIDE: the whole column projects into rows [0, R - 1) (checked per column, uniform), so the
 // row loops need no clamping to the row window.
+// Every lane runs five faces: when nz is not a multiple of 4, the last run continues past the
+// top slice with zero-valued slices on the same face lines (the callers' fast and inside tests
+// cover faces up to nz rounded up to a multiple of 4), which only adds zero row values.
 template <int K, int NC, bool NORM, bool INSIDE>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
                                            const float (&w)[K], int *accs, int SW, int R,
                                            int lane)
 {
-    const float fR = (float)R;
+    const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
     for (int zb = 0; zb < nz; zb += 256) {
         const int z0 = zb + 4 * lane;
         if (z0 >= nz)
@@ -517,70 +520,75 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
             for (int q = 0; q < 4; ++q)
                 v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
         }
-        const int nq = min(4, nz - z0);
-        float p[5], qf[5];
+        // faces z0 .. z0 + 4 on the near and far lines; m = p + q (twice the face centre)
+        const float z0f = (float)z0;
+        const float an0 = fmaf(bn, z0f, an), af0 = fmaf(bf, z0f, af);
+        float p[5], qf[5], m[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            const float zf = (float)(z0 + min(f, nq));
-            const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
+            const float vn = f == 0 ? an0 : fmaf((float)f, bn, an0);
+            const float vf = f == 0 ? af0 : fmaf((float)f, bf, af0);
             p[f] = fminf(vn, vf);
             qf[f] = fmaxf(vn, vf);
+            m[f] = p[f] + qf[f];
         }
         // skip runs entirely outside the row window
-        if (!INSIDE && (qf[nq] < 0.0f || p[0] >= fR))
+        if (!INSIDE && (qf[4] < 0.0f || p[0] >= fR))
             continue;
-        if constexpr (NORM) {
-            // recon mode: each voxel's axial trapezoid normalised to unit area
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (q < nq)
-                    v[q] *= fdiv(2.0f, (p[q + 1] + qf[q + 1]) - (p[q] + qf[q]));
-        }
-        int tp = INSIDE ? (int)floorf(p[0]) : max((int)floorf(p[0]), -1);   // C = 0 at floor(p0)
-        // C and the prefix S stay in FP32: a run holds four slices, so they are sums of a few
-        // terms and the row differences C(j+1) - C(j) lose at most a few ulps of x.
-        float Cprev = 0.0f, S = 0.0f;
-        float vm1 = 0.0f;
-        auto emit = [&](int t, float C) {
-            const float rv = C - Cprev;
-            int *a = accs + (t - 1) * SW;
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-                atomicAdd(a + k, to_fixed(rv * w[k]));
-            Cprev = C;
-        };
+        float area[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (q < nq) {
-                // branch-free C(t) - S over face q and voxel q's plateau:
-                //   v_q (min(t - p, w)^2 / (2w) + max(t - q, 0)) - v_{q-1} max(q - t, 0)^2 / (2w)
-                const float pz = p[q], qz = qf[q], wz = qz - pz;
-                const float h = wz > 1e-12f ? 0.5f * fast_rcp(wz) : 0.0f;
-                const int te = INSIDE ? (int)ceilf(p[q + 1]) - 1
-                                      : min((int)ceilf(fminf(p[q + 1], fR + 1.0f)) - 1, R);
-                for (int t = tp + 1; t <= te; ++t) {
-                    // with u = t - q and e = max(u, 0): min(t - p, w) = (t - p) - e and
-                    // max(q - t, 0) = e - u (no min/max of loop-invariant operands)
-                    const float ft = (float)t;
-                    const float u = ft - qz, e = fmaxf(u, 0.0f);
-                    const float d1 = (ft - pz) - e, d2 = e - u;
-                    const float local = fmaf(v[q], fmaf(d1 * d1, h, e), -vm1 * (d2 * d2 * h));
-                    emit(t, S + local);
-                }
-                tp = max(tp, te);
-                const float area = 0.5f * ((p[q + 1] + qf[q + 1]) - (pz + qz));
-                S = fmaf(v[q], area, S);
-                vm1 = v[q];
-            }
+            area[q] = 0.5f * (m[q + 1] - m[q]);
+            if constexpr (NORM)   // recon mode: each voxel's axial trapezoid normalised to unit area
+                v[q] = fdiv(v[q], area[q]);
         }
-        // above the run's top face: S minus the falling ramp of its last voxel
+        // ft: the next row edge to close (row ft - 1; row -1 is the guard row), ap: that row.
+        // cp: C at the previous edge minus the prefix S_q of the current face q, so that the
+        // row value is local(t) - cp with local(t) = C(t) - S_q a sum of a few small terms.
+        float ft = INSIDE ? floorf(p[0]) + 1.0f : fmaxf(floorf(p[0]), -1.0f) + 1.0f;
+        int *ap = accs - SW + __umul24((unsigned)ft, SW);
+        float cp = 0.0f;
+        auto emit = [&](float local) {
+            const float rv = local - cp;
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                atomicAdd(ap + k, to_fixed(rv * w[k]));
+            cp = local;
+            ap += SW;
+            ft += 1.0f;
+        };
+        // Inside face q (or on voxel q's plateau above it), with u = t - q_q, e = max(u, 0),
+        // d2 = e - u = max(q_q - t, 0) and d1 = w_q - d2 = min(t - p_q, w_q):
+        //   local = v_q (d1^2 / (2 w_q) + e) - v_{q-1} d2^2 / (2 w_q)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float wq = qf[q] - p[q];
+            const float h = 0.5f * fast_rcp(fmaxf(wq, 1e-30f));
+            const float fte = INSIDE ? ceilf(p[q + 1]) - 1.0f : ceilf(fminf(p[q + 1], fR1)) - 1.0f;
+            if (q == 0) {   // no voxel below the run
+                while (ft <= fte) {
+                    const float u = ft - qf[0], e = fmaxf(u, 0.0f);
+                    const float d1 = wq - (e - u);
+                    emit(v[0] * fmaf(d1 * d1, h, e));
+                }
+            } else {
+                const float nvh = -v[q - 1] * h;
+                while (ft <= fte) {
+                    const float u = ft - qf[q], e = fmaxf(u, 0.0f);
+                    const float d2 = e - u, d1 = wq - d2;
+                    emit(fmaf(v[q], fmaf(d1 * d1, h, e), (d2 * d2) * nvh));
+                }
+            }
+            cp = fmaf(-v[q], area[q], cp);   // S_{q+1} = S_q + v_q area_q
+        }
+        // above the run's top face: voxel 3's falling ramp over face 4
         {
-            const float pt = p[nq], qt = qf[nq], wt = qt - pt;
-            const float h = wt > 1e-12f ? 0.5f * fast_rcp(wt) : 0.0f;
-            const int te = INSIDE ? (int)floorf(qt) + 1 : min((int)floorf(fminf(qt, fR)) + 1, R);
-            for (int t = tp + 1; t <= te; ++t) {
-                const float d2 = fmaxf(qt - (float)t, 0.0f);
-                emit(t, fmaf(-vm1, d2 * d2 * h, S));
+            const float h = 0.5f * fast_rcp(fmaxf(qf[4] - p[4], 1e-30f));
+            const float nvh = -v[3] * h;
+            const float fte = INSIDE ? floorf(qf[4]) + 1.0f : floorf(fminf(qf[4], fRm1)) + 1.0f;
+            while (ft <= fte) {
+                const float d2 = fmaxf(qf[4] - ft, 0.0f);
+                emit((d2 * d2) * nvh);
             }
         }
     }
@@ -821,8 +829,10 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                 // broadcast loop below reads the answers from two masks
                 uint64_t m_fast = 0, m_inside = 0;
                 if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
-                    const bool fast = nc > 0 && sf_fast_ok(an, bn, af, bf, P.nz);
-                    const float fnz = (float)P.nz;
+                    // the runs cover faces up to nz rounded up to a multiple of 4
+                    const int nz4 = (P.nz + 3) & ~3;
+                    const bool fast = nc > 0 && sf_fast_ok(an, bn, af, bf, nz4);
+                    const float fnz = (float)nz4;
                     const bool inside = fast && fminf(an, af) >= 0.0f &&
                                         fmaxf(fmaf(bn, fnz, an), fmaf(bf, fnz, af)) < (float)(R - 1);
                     m_fast = __ballot(fast);
