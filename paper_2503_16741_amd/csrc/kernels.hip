@@ -1056,14 +1056,18 @@ __device__ __forceinline__ bool sf_bwd_fast_ok(float an, float bn, float af, flo
 }
 
 // INSIDE: every row the walk loads (floor(p_first) .. floor(q_last) + 1) lies on the detector
-// and the K footprint columns cs .. cs + K - 1 exist, so rows are read through a running row
-// pointer (one add per row, the K columns at immediate offsets); otherwise rows are read at
+// and the K footprint columns cs .. cs + K - 1 exist, so rows are read at a running 32-bit
+// offset (one add per row, the K columns at immediate offsets); otherwise rows are read at
 // clamped, in-bounds indices (32-bit offsets within the view) and outside rows count zero.
+// All NQ + 1 faces of the chunk are walked: in a partial last chunk the faces past the top
+// slice follow the same lines (the callers' fast and inside tests cover all NQ + 1 faces) and
+// their slices are dropped at write-out.  D is carried doubled (2D = 2R - 2J), which removes
+// two multiplications per face; the accumulation takes the factor 1/2 back.
 template <int K, int NQ, bool NORM, bool INSIDE>
 __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_t row_stride,
                                             int cs, int nu, int rows, const float (&w)[K],
                                             float an, float bn, float af, float bf, int zc0,
-                                            int nq, float (&acc)[NQ])
+                                            float (&acc)[NQ])
 {
     const uint32_t rs = (uint32_t)row_stride;
     uint32_t cidx[K];
@@ -1081,59 +1085,72 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
     };
     const float fr = (float)rows;
     const float zs = (float)zc0;
-    int jc = (int)floorf(fminf(fmaxf(fminf(fmaf(bn, zs, an), fmaf(bf, zs, af)), -1.0f), fr));
-    const float *rowp = yv + cs + (int64_t)(jc + 1) * row_stride;   // row jc + 1 (INSIDE)
+    const float an0 = fmaf(bn, zs, an), af0 = fmaf(bf, zs, af);
+    const float p0 = fminf(an0, af0);
+    int jc = INSIDE ? (int)floorf(p0) : (int)floorf(fminf(fmaxf(p0, -1.0f), fr));
+    // INSIDE: byte offset of row jc + 1, column cs (a 32-bit offset from the view's base, the
+    // K columns at immediate offsets)
+    const uint32_t rsb = rs * 4u;
+    uint32_t offb = ((uint32_t)(jc + 1) * rs + (uint32_t)cs) * 4u;
+    auto row_at = [&](uint32_t ob) -> const float * {
+        return reinterpret_cast<const float *>(reinterpret_cast<const char *>(yv) + ob);
+    };
     auto load_next = [&]() -> float {
         if constexpr (INSIDE) {
+            const float *rp = row_at(offb);
             float r = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                r = fmaf(w[k], rowp[k], r);
+                r = fmaf(w[k], rp[k], r);
             return r;
         } else {
             return load_row(jc + 1);
         }
     };
-    float rc = INSIDE ? 0.0f : load_row(jc);
+    float rc = 0.0f;
     if constexpr (INSIDE) {
+        const float *rp = row_at(offb - rsb);
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            rc = fmaf(w[k], rowp[k - (int64_t)row_stride], rc);
+            rc = fmaf(w[k], rp[k], rc);
+    } else {
+        rc = load_row(jc);
     }
-    float rn = load_next(), rp = 0.0f, RP = 0.0f, Dprev = 0.0f;
+    float rn = load_next(), rp = 0.0f, RP = 0.0f, D2prev = 0.0f;
     float mprev = 0.0f;                               // p + q of the previous face (NORM)
 #pragma unroll
     for (int f = 0; f <= NQ; ++f) {
-        if (f <= nq) {
-            const float zf = (float)(zc0 + f);
-            const float vn = fmaf(bn, zf, an), vf = fmaf(bf, zf, af);
-            const float p = fminf(vn, vf), q = fmaxf(vn, vf), w = q - p;
-            const int jq = (int)floorf(fminf(fmaxf(q, -1.0f), fr));
-            while (jc < jq) {
-                RP += rc;
-                rp = rc;
-                rc = rn;
-                ++jc;
-                if constexpr (INSIDE)
-                    rowp += row_stride;
-                rn = load_next();
-            }
-            const float R = fmaf(q - (float)jc, rc, RP);
-            // ramp-weighted integral of r over the face (branch-free: a <= 0 when the face lies
-            // within row jc, w <= eps for a degenerate face)
-            const float a = fmaxf((float)jc - p, 0.0f);
-            const float h = w > 1e-12f ? 0.5f * fast_rcp(w) : 0.0f;
-            const float J = fmaf(rp - rc, a * a * h, rc * 0.5f * w);
-            const float D = R - J;
-            if (f > 0) {
-                if constexpr (NORM)   // recon mode: divide by the slice's trapezoid area
-                    acc[f - 1] += (D - Dprev) * fdiv(2.0f, (p + q) - mprev);
-                else
-                    acc[f - 1] += D - Dprev;
-            }
-            Dprev = D;
-            mprev = p + q;
+        const float vn = f == 0 ? an0 : fmaf((float)f, bn, an0);
+        const float vf = f == 0 ? af0 : fmaf((float)f, bf, af0);
+        const float p = fminf(vn, vf), q = fmaxf(vn, vf), wf = q - p;
+        const int jq = INSIDE ? (int)floorf(q) : (int)floorf(fminf(fmaxf(q, -1.0f), fr));
+        while (jc < jq) {
+            RP += rc;
+            rp = rc;
+            rc = rn;
+            ++jc;
+            if constexpr (INSIDE)
+                offb += rsb;
+            rn = load_next();
         }
+        const float fjc = (float)jc;
+        // ramp-weighted integral of r over the face, doubled (branch-free: a <= 0 when the face
+        // lies within row jc; a <= w keeps a^2 / w finite for a degenerate face)
+        const float a = fmaxf(fjc - p, 0.0f);
+        const float J2 = fmaf(rp - rc, (a * a) * fast_rcp(fmaxf(wf, 1e-30f)), rc * wf);
+        const float D2 = fmaf(2.0f, fmaf(q - fjc, rc, RP), -J2);
+        if (f > 0) {
+            if constexpr (NORM)   // recon mode: divide by the slice's trapezoid area
+                acc[f - 1] += fdiv(D2 - D2prev, (p + q) - mprev);
+            else
+                acc[f - 1] = fmaf(0.5f, D2 - D2prev, acc[f - 1]);
+            // keep the update here: sunk to the end of the view, it would hold every face's
+            // walk state live across the later faces' row loops
+            asm volatile("" : "+v"(acc[f - 1]));
+        }
+        D2prev = D2;
+        if constexpr (NORM)
+            mprev = p + q;
     }
 }
 
@@ -1209,10 +1226,9 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                 } else {
                     const float an = fmaf(col.An, zb0, V.cv), bn = col.An * P.dz;
                     const float af = fmaf(col.Af, zb0, V.cv), bf = col.Af * P.dz;
-                    const int nq = min(kZChunk, nzv - zc0);
-                    if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + nq - 1)) {
-                        // rows loaded: floor(p at zc0) .. floor(q at zc0 + nq) + 1
-                        const float z0f = (float)zc0, z1f = (float)(zc0 + nq);
+                    if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + kZChunk - 1)) {
+                        // rows loaded: floor(p at zc0) .. floor(q at zc0 + kZChunk) + 1
+                        const float z0f = (float)zc0, z1f = (float)(zc0 + kZChunk);
                         const float plo = fminf(fmaf(bn, z0f, an), fmaf(bf, z0f, af));
                         const float qhi = fmaxf(fmaf(bn, z1f, an), fmaf(bf, z1f, af));
                         const bool inside = plo >= 0.0f && qhi < (float)(rows_total - 2) &&
@@ -1220,11 +1236,11 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                         if (inside)
                             sf_bwd_fast<K, kZChunk, METHOD == kSFR, true>(
                                 yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
-                                zc0, nq, acc);
+                                zc0, acc);
                         else
                             sf_bwd_fast<K, kZChunk, METHOD == kSFR, false>(
                                 yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
-                                zc0, nq, acc);
+                                zc0, acc);
                         continue;
                     }
 #pragma unroll
