@@ -625,7 +625,9 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
                                            const float (&fx)[K], int nc, int *accs,
                                            int SW, int R, int lane)
 {
-    const float fR = (float)R;
+    // Every lane runs five boundaries; past the top slice (nz not a multiple of 4) the run
+    // continues with zero-valued slices, which only adds zero row values.
+    const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
     for (int zb = 0; zb < nz; zb += 256) {
         const int z0 = zb + 4 * lane;
         if (z0 >= nz)
@@ -639,37 +641,39 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
             for (int q = 0; q < 4; ++q)
                 v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
         }
-        const int nq = min(4, nz - z0);
+        const float z0f = (float)z0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k >= nc)
                 break;
             float zt[5];
+            zt[0] = fmaf(be[k], z0f, al[k]);
 #pragma unroll
-            for (int f = 0; f < 5; ++f)
-                zt[f] = fmaf(be[k], (float)(z0 + min(f, nq)), al[k]);
-            if (zt[nq] < 0.0f || zt[0] >= fR)
+            for (int f = 1; f < 5; ++f)
+                zt[f] = fmaf((float)f, be[k], zt[0]);
+            if (zt[4] < 0.0f || zt[0] >= fR)
                 continue;
-            int tp = max((int)floorf(zt[0]), -1);
-            float Cprev = 0.0f, S = 0.0f;          // FP32 prefix of the run (a few terms)
-            int *ak = accs + k;
-            auto emit = [&](int t, float C) {      // t - 1 = -1 lands in the guard row
-                atomicAdd(ak + (t - 1) * SW, to_fixed((C - Cprev) * fx[k]));
-                Cprev = C;
+            // ft: the next row edge to close (row ft - 1; row -1 is the guard row), ap: that
+            // row's cell k; cp: C at the previous edge minus the prefix of the current slice
+            float ft = fmaxf(floorf(zt[0]), -1.0f) + 1.0f;
+            int *ap = accs + k - SW + __umul24((unsigned)ft, SW);
+            float cp = 0.0f;
+            auto emit = [&](float local) {
+                atomicAdd(ap, to_fixed((local - cp) * fx[k]));
+                cp = local;
+                ap += SW;
+                ft += 1.0f;
             };
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (q < nq) {
-                    const int te = min((int)ceilf(fminf(zt[q + 1], fR + 1.0f)) - 1, R);
-                    for (int t = tp + 1; t <= te; ++t)
-                        emit(t, fmaf(v[q], (float)t - zt[q], S));
-                    tp = max(tp, te);
-                    S = fmaf(v[q], zt[q + 1] - zt[q], S);
-                }
+                const float fte = ceilf(fminf(zt[q + 1], fR1)) - 1.0f;
+                while (ft <= fte)
+                    emit(v[q] * (ft - zt[q]));
+                cp = fmaf(-v[q], zt[q + 1] - zt[q], cp);
             }
-            const int te = min((int)floorf(fminf(zt[nq], fR)) + 1, R);
-            for (int t = tp + 1; t <= te; ++t)
-                emit(t, S);
+            const float fte = floorf(fminf(zt[4], fRm1)) + 1.0f;
+            while (ft <= fte)
+                emit(0.0f);
         }
     }
 }
@@ -1333,35 +1337,46 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                         // zeta_f = al_k + be_k f, which tile the axis; the slice's gather is
                         // R_k(zeta_{z+1}) - R_k(zeta_z), R_k the running integral of the column's
                         // rows (clamped to the detector), so each row is loaded once.
-                        const int nq = min(kZChunk, nzv - zc0);
+                        // all kZChunk + 1 boundaries are walked (clamped to the detector);
+                        // slices past the top one are dropped at write-out
                         const float fr = (float)rows_total;
+                        const uint32_t rsb = (uint32_t)P.sino_row_stride * 4u;
+                        const float zc0f = (float)zc0;
 #pragma unroll
                         for (int k = 0; k < K; ++k) {
                             if (k >= nc)
                                 break;
-                            const float *yk = yc0 + k;
-                            const uint32_t rs = (uint32_t)P.sino_row_stride;
+                            const float a0 = fmaf(be[k], zc0f, al[k]);
                             float RP = 0.0f, Dprev = 0.0f, rc = 0.0f;
                             int jc = 0;
+                            uint32_t offb = 0;     // byte offset of row jc, cell cs + k, in the view
+                            auto row_at = [&](uint32_t ob) -> float {
+                                return *reinterpret_cast<const float *>(
+                                    reinterpret_cast<const char *>(yv) + ob);
+                            };
 #pragma unroll
                             for (int f = 0; f <= kZChunk; ++f) {
-                                if (f <= nq) {
-                                    const float t = fminf(fmaxf(fmaf(be[k], (float)(zc0 + f), al[k]), 0.0f), fr);
-                                    const int jt = min((int)t, rows_total - 1);
-                                    if (f == 0) {
-                                        jc = jt;
-                                        rc = yk[(uint32_t)jc * rs];
-                                    }
-                                    while (jc < jt) {
-                                        RP += rc;
-                                        ++jc;
-                                        rc = yk[(uint32_t)jc * rs];
-                                    }
-                                    const float D = fmaf(t - (float)jc, rc, RP);
-                                    if (f > 0)
-                                        acc[f - 1] = fmaf(fx[k], D - Dprev, acc[f - 1]);
-                                    Dprev = D;
+                                const float t = fminf(fmaxf(f == 0 ? a0 : fmaf((float)f, be[k], a0), 0.0f), fr);
+                                const int jt = min((int)t, rows_total - 1);
+                                if (f == 0) {
+                                    jc = jt;
+                                    offb = ((uint32_t)jc * (uint32_t)P.sino_row_stride +
+                                            (uint32_t)(cs + k)) * 4u;
+                                    rc = row_at(offb);
                                 }
+                                while (jc < jt) {
+                                    RP += rc;
+                                    ++jc;
+                                    offb += rsb;
+                                    rc = row_at(offb);
+                                }
+                                const float D = fmaf(t - (float)jc, rc, RP);
+                                if (f > 0) {
+                                    acc[f - 1] = fmaf(fx[k], D - Dprev, acc[f - 1]);
+                                    // keep the update here (see sf_bwd_fast)
+                                    asm volatile("" : "+v"(acc[f - 1]));
+                                }
+                                Dprev = D;
                             }
                         }
                         continue;
