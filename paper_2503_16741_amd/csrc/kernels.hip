@@ -1247,7 +1247,9 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                                 zc0, acc);
                         continue;
                     }
-#pragma unroll
+                    // per-voxel fallback (rare: overlapping or wide faces), kept rolled so
+                    // that it does not set the kernel's register count
+#pragma unroll 1
                     for (int q = 0; q < kZChunk; ++q) {
                         const int z = zc0 + q;
                         if (z < nzv) {
@@ -1264,7 +1266,9 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                             });
                             if constexpr (METHOD == kSFR)
                                 s = fdiv(s, trap_area(tr));
-                            acc[q] += s;
+#pragma unroll
+                            for (int qq = 0; qq < kZChunk; ++qq)
+                                acc[qq] += qq == q ? s : 0.0f;
                         }
                     }
                 }
