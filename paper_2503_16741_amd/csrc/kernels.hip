@@ -507,6 +507,9 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                                            int lane)
 {
     const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
+    // every slice's trapezoid has the same area, the distance between consecutive face centres
+    const float area = 0.5f * (bn + bf);
+    const float inv_area = NORM ? fast_rcp(area) : 1.0f;
     for (int zb = 0; zb < nz; zb += 256) {
         const int z0 = zb + 4 * lane;
         if (z0 >= nz)
@@ -520,33 +523,36 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
             for (int q = 0; q < 4; ++q)
                 v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
         }
-        // faces z0 .. z0 + 4 on the near and far lines; m = p + q (twice the face centre)
+        // faces z0 .. z0 + 4 on the near and far lines, in rows relative to the run's base row
+        // edge (the subtraction is exact), so the face offsets within the run and the row
+        // edges are accurate to a few ulps of the run's extent rather than of the row index
         const float z0f = (float)z0;
         const float an0 = fmaf(bn, z0f, an), af0 = fmaf(bf, z0f, af);
-        float p[5], qf[5], m[5];
+        const float base = floorf(fminf(an0, af0));
+        const float an0r = an0 - base, af0r = af0 - base;
+        float p[5], qf[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            const float vn = f == 0 ? an0 : fmaf((float)f, bn, an0);
-            const float vf = f == 0 ? af0 : fmaf((float)f, bf, af0);
+            const float vn = f == 0 ? an0r : fmaf((float)f, bn, an0r);
+            const float vf = f == 0 ? af0r : fmaf((float)f, bf, af0r);
             p[f] = fminf(vn, vf);
             qf[f] = fmaxf(vn, vf);
-            m[f] = p[f] + qf[f];
         }
         // skip runs entirely outside the row window
-        if (!INSIDE && (qf[4] < 0.0f || p[0] >= fR))
+        if (!INSIDE && (qf[4] < -base || base >= fR))
             continue;
-        float area[4];
+        if constexpr (NORM) {   // recon mode: each voxel's axial trapezoid normalised to unit area
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            area[q] = 0.5f * (m[q + 1] - m[q]);
-            if constexpr (NORM)   // recon mode: each voxel's axial trapezoid normalised to unit area
-                v[q] = fdiv(v[q], area[q]);
+            for (int q = 0; q < 4; ++q)
+                v[q] *= inv_area;
         }
-        // ft: the next row edge to close (row ft - 1; row -1 is the guard row), ap: that row.
-        // cp: C at the previous edge minus the prefix S_q of the current face q, so that the
-        // row value is local(t) - cp with local(t) = C(t) - S_q a sum of a few small terms.
-        float ft = INSIDE ? floorf(p[0]) + 1.0f : fmaxf(floorf(p[0]), -1.0f) + 1.0f;
-        int *ap = accs - SW + __umul24((unsigned)ft, SW);
+        // ft: the next row edge to close (relative; row base + ft - 1, row -1 being the guard
+        // row), ap: that row.  cp: C at the previous edge minus the prefix S_q of the current
+        // face q, so that the row value is local(t) - cp with local(t) = C(t) - S_q a sum of a
+        // few small terms.
+        float ft = INSIDE ? 1.0f : fmaxf(base, -1.0f) + 1.0f - base;
+        int *ap = accs - SW + __umul24((unsigned)(ft + base), SW);
+        const float lim1 = fR1 - base, limm1 = fRm1 - base;   // row window (relative)
         float cp = 0.0f;
         auto emit = [&](float local) {
             const float rv = local - cp;
@@ -564,7 +570,7 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
         for (int q = 0; q < 4; ++q) {
             const float wq = qf[q] - p[q];
             const float h = 0.5f * fast_rcp(fmaxf(wq, 1e-30f));
-            const float fte = INSIDE ? ceilf(p[q + 1]) - 1.0f : ceilf(fminf(p[q + 1], fR1)) - 1.0f;
+            const float fte = INSIDE ? ceilf(p[q + 1]) - 1.0f : ceilf(fminf(p[q + 1], lim1)) - 1.0f;
             if (q == 0) {   // no voxel below the run
                 while (ft <= fte) {
                     const float u = ft - qf[0], e = fmaxf(u, 0.0f);
@@ -579,13 +585,13 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                     emit(fmaf(v[q], fmaf(d1 * d1, h, e), (d2 * d2) * nvh));
                 }
             }
-            cp = fmaf(-v[q], area[q], cp);   // S_{q+1} = S_q + v_q area_q
+            cp = fmaf(-v[q], area, cp);   // S_{q+1} = S_q + v_q area
         }
         // above the run's top face: voxel 3's falling ramp over face 4
         {
             const float h = 0.5f * fast_rcp(fmaxf(qf[4] - p[4], 1e-30f));
             const float nvh = -v[3] * h;
-            const float fte = INSIDE ? floorf(qf[4]) + 1.0f : floorf(fminf(qf[4], fRm1)) + 1.0f;
+            const float fte = INSIDE ? floorf(qf[4]) + 1.0f : floorf(fminf(qf[4], limm1)) + 1.0f;
             while (ft <= fte) {
                 const float d2 = fmaxf(qf[4] - ft, 0.0f);
                 emit((d2 * d2) * nvh);
@@ -646,17 +652,22 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
         for (int k = 0; k < K; ++k) {
             if (k >= nc)
                 break;
+            // boundaries relative to the run's base row edge (exact subtraction)
+            const float z00 = fmaf(be[k], z0f, al[k]);
+            const float base = floorf(z00);
             float zt[5];
-            zt[0] = fmaf(be[k], z0f, al[k]);
+            zt[0] = z00 - base;
 #pragma unroll
             for (int f = 1; f < 5; ++f)
                 zt[f] = fmaf((float)f, be[k], zt[0]);
-            if (zt[4] < 0.0f || zt[0] >= fR)
+            if (zt[4] < -base || base >= fR)
                 continue;
-            // ft: the next row edge to close (row ft - 1; row -1 is the guard row), ap: that
-            // row's cell k; cp: C at the previous edge minus the prefix of the current slice
-            float ft = fmaxf(floorf(zt[0]), -1.0f) + 1.0f;
-            int *ap = accs + k - SW + __umul24((unsigned)ft, SW);
+            // ft: the next row edge to close (relative; row base + ft - 1, row -1 being the
+            // guard row), ap: that row's cell k; cp: C at the previous edge minus the prefix of
+            // the current slice
+            float ft = fmaxf(base, -1.0f) + 1.0f - base;
+            int *ap = accs + k - SW + __umul24((unsigned)(ft + base), SW);
+            const float lim1 = fR1 - base, limm1 = fRm1 - base;
             float cp = 0.0f;
             auto emit = [&](float local) {
                 atomicAdd(ap, to_fixed((local - cp) * fx[k]));
@@ -666,12 +677,12 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
             };
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float fte = ceilf(fminf(zt[q + 1], fR1)) - 1.0f;
+                const float fte = ceilf(fminf(zt[q + 1], lim1)) - 1.0f;
                 while (ft <= fte)
                     emit(v[q] * (ft - zt[q]));
-                cp = fmaf(-v[q], zt[q + 1] - zt[q], cp);
+                cp = fmaf(-v[q], be[k], cp);     // every slice maps to be rows
             }
-            const float fte = floorf(fminf(zt[4], fRm1)) + 1.0f;
+            const float fte = floorf(fminf(zt[4], limm1)) + 1.0f;
             while (ft <= fte)
                 emit(0.0f);
         }
