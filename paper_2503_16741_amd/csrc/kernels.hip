@@ -1110,17 +1110,32 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
     auto row_at = [&](uint32_t ob) -> const float * {
         return reinterpret_cast<const float *>(reinterpret_cast<const char *>(yv) + ob);
     };
-    auto load_next = [&]() -> float {
+    // Row jc + 1 is fetched ahead as raw values and weighted only when the walk moves onto it,
+    // so its load latency overlaps the work in between (weighting it at once would wait for
+    // the load right after issuing it).
+    float nraw[K];
+    bool nvalid = true;
+    auto fetch_next = [&]() {
         if constexpr (INSIDE) {
             const float *rp = row_at(offb);
-            float r = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                r = fmaf(w[k], rp[k], r);
-            return r;
+                nraw[k] = rp[k];
         } else {
-            return load_row(jc + 1);
+            const int j = jc + 1;
+            const uint32_t off = (uint32_t)min(max(j, 0), rows - 1) * rs;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                nraw[k] = yv[off + cidx[k]];
+            nvalid = j >= 0 && j < rows;
         }
+    };
+    auto weigh_next = [&]() -> float {
+        float r = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            r = fmaf(w[k], nraw[k], r);
+        return nvalid ? r : 0.0f;
     };
     float rc = 0.0f;
     if constexpr (INSIDE) {
@@ -1131,7 +1146,8 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
     } else {
         rc = load_row(jc);
     }
-    float rn = load_next(), rp = 0.0f, RP = 0.0f, D2prev = 0.0f;
+    fetch_next();
+    float rp = 0.0f, RP = 0.0f, D2prev = 0.0f;
     float mprev = 0.0f;                               // p + q of the previous face (NORM)
 #pragma unroll
     for (int f = 0; f <= NQ; ++f) {
@@ -1142,11 +1158,11 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
         while (jc < jq) {
             RP += rc;
             rp = rc;
-            rc = rn;
+            rc = weigh_next();
             ++jc;
             if constexpr (INSIDE)
                 offb += rsb;
-            rn = load_next();
+            fetch_next();
         }
         const float fjc = (float)jc;
         // ramp-weighted integral of r over the face, doubled (branch-free: a <= 0 when the face
@@ -1166,6 +1182,147 @@ __device__ __forceinline__ void sf_bwd_fast(const float *__restrict__ yv, int64_
         D2prev = D2;
         if constexpr (NORM)
             mprev = p + q;
+    }
+}
+
+// Gather of one view into a lane's kZChunk voxels of a circular-scan column (SF / recon-mode
+// SF): the walk when the column's faces allow it, otherwise the per-voxel fallback.
+template <int K, bool NORM>
+__device__ __forceinline__ void sf_circ_gather(const Params &P, const float *__restrict__ yv, int cs,
+                                               int nc, const float (&w)[K], float an, float bn,
+                                               float af, float bf, int zc0,
+                                               float (&acc)[kZChunk])
+{
+    const int rows_total = P.nv, nzv = P.nz;
+    const float *yc0 = yv + cs;
+    if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + kZChunk - 1)) {
+        // rows loaded: floor(p at zc0) .. floor(q at zc0 + kZChunk) + 1
+        const float z0f = (float)zc0, z1f = (float)(zc0 + kZChunk);
+        const float plo = fminf(fmaf(bn, z0f, an), fmaf(bf, z0f, af));
+        const float qhi = fmaxf(fmaf(bn, z1f, an), fmaf(bf, z1f, af));
+        const bool inside = plo >= 0.0f && qhi < (float)(rows_total - 2) &&
+                            cs + K <= P.nu;
+        if (inside)
+            sf_bwd_fast<K, kZChunk, NORM, true>(
+                yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
+                zc0, acc);
+        else
+            sf_bwd_fast<K, kZChunk, NORM, false>(
+                yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
+                zc0, acc);
+        return;
+    }
+    // per-voxel fallback (rare: overlapping or wide faces), kept rolled so
+    // that it does not set the kernel's register count
+#pragma unroll 1
+    for (int q = 0; q < kZChunk; ++q) {
+        const int z = zc0 + q;
+        if (z < nzv) {
+            const Trap tr = sf_axial(an, bn, af, bf, (float)z, P.eps);
+            float s = 0.0f;
+            for_rows(tr, rows_total, [&](int j, float F) {
+                const float *yr = yc0 + (int64_t)j * P.sino_row_stride;
+                float rs = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k < nc)
+                        rs = fmaf(w[k], yr[k], rs);
+                s = fmaf(F, rs, s);
+            });
+            if constexpr (NORM)
+                s = fdiv(s, trap_area(tr));
+#pragma unroll
+            for (int qq = 0; qq < kZChunk; ++qq)
+                acc[qq] += qq == q ? s : 0.0f;
+        }
+    }
+}
+
+// Gather of one view into a lane's kZChunk voxels of a circular-scan column (DD): the
+// running-integral walk when every footprint column maps z increasingly, otherwise per voxel.
+template <int K>
+__device__ __forceinline__ void dd_circ_gather(const Params &P, const float *__restrict__ yv, int cs,
+                                               int nc, const float (&fx)[K], const float (&al)[K],
+                                               const float (&be)[K], int zc0,
+                                               float (&acc)[kZChunk])
+{
+    const int rows_total = P.nv, nzv = P.nz;
+    const float *yc0 = yv + cs;
+    bool walk = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        walk = walk && !(k < nc && !(be[k] > 0.0f));
+    if (CTP_BWD_FAST && walk) {
+        // Footprint column k maps slice z onto rows [zeta_z, zeta_{z+1}],
+        // zeta_f = al_k + be_k f, which tile the axis; the slice's gather is
+        // R_k(zeta_{z+1}) - R_k(zeta_z), R_k the running integral of the column's
+        // rows (clamped to the detector), so each row is loaded once.
+        // all kZChunk + 1 boundaries are walked (clamped to the detector);
+        // slices past the top one are dropped at write-out
+        const float fr = (float)rows_total;
+        const uint32_t rsb = (uint32_t)P.sino_row_stride * 4u;
+        const float zc0f = (float)zc0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k >= nc)
+                break;
+            const float a0 = fmaf(be[k], zc0f, al[k]);
+            float RP = 0.0f, Dprev = 0.0f, rc = 0.0f;
+            int jc = 0;
+            uint32_t offb = 0;     // byte offset of row jc, cell cs + k, in the view
+            auto row_at = [&](uint32_t ob) -> float {
+                return *reinterpret_cast<const float *>(
+                    reinterpret_cast<const char *>(yv) + ob);
+            };
+#pragma unroll
+            for (int f = 0; f <= kZChunk; ++f) {
+                const float t = fminf(fmaxf(f == 0 ? a0 : fmaf((float)f, be[k], a0), 0.0f), fr);
+                const int jt = min((int)t, rows_total - 1);
+                if (f == 0) {
+                    jc = jt;
+                    offb = ((uint32_t)jc * (uint32_t)P.sino_row_stride +
+                            (uint32_t)(cs + k)) * 4u;
+                    rc = row_at(offb);
+                }
+                while (jc < jt) {
+                    RP += rc;
+                    ++jc;
+                    offb += rsb;
+                    rc = row_at(offb);
+                }
+                const float D = fmaf(t - (float)jc, rc, RP);
+                if (f > 0) {
+                    acc[f - 1] = fmaf(fx[k], D - Dprev, acc[f - 1]);
+                    // keep the update here (see sf_bwd_fast)
+                    asm volatile("" : "+v"(acc[f - 1]));
+                }
+                Dprev = D;
+            }
+        }
+        return;
+    }
+    // per-voxel fallback, kept rolled (see sf_circ_gather)
+#pragma unroll 1
+    for (int q = 0; q < kZChunk; ++q) {
+        const int z = zc0 + q;
+        if (z < nzv) {
+            float s = 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k < nc) {
+                    const float zl = fmaf(be[k], (float)z, al[k]);
+                    const float zh = zl + be[k];
+                    float rs = 0.0f;
+                    for_dd_rows(zl, zh, rows_total, [&](int j, float wz) {
+                        rs = fmaf(wz, yc0[(int64_t)j * P.sino_row_stride + k], rs);
+                    });
+                    s = fmaf(fx[k], rs, s);
+                }
+            }
+#pragma unroll
+            for (int qq = 0; qq < kZChunk; ++qq)
+                acc[qq] += qq == q ? s : 0.0f;
+        }
     }
 }
 
@@ -1241,47 +1398,8 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                 } else {
                     const float an = fmaf(col.An, zb0, V.cv), bn = col.An * P.dz;
                     const float af = fmaf(col.Af, zb0, V.cv), bf = col.Af * P.dz;
-                    if (CTP_BWD_FAST && sf_bwd_fast_ok(an, bn, af, bf, zc0, zc0 + kZChunk - 1)) {
-                        // rows loaded: floor(p at zc0) .. floor(q at zc0 + kZChunk) + 1
-                        const float z0f = (float)zc0, z1f = (float)(zc0 + kZChunk);
-                        const float plo = fminf(fmaf(bn, z0f, an), fmaf(bf, z0f, af));
-                        const float qhi = fmaxf(fmaf(bn, z1f, an), fmaf(bf, z1f, af));
-                        const bool inside = plo >= 0.0f && qhi < (float)(rows_total - 2) &&
-                                            cs + K <= P.nu;
-                        if (inside)
-                            sf_bwd_fast<K, kZChunk, METHOD == kSFR, true>(
-                                yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
-                                zc0, acc);
-                        else
-                            sf_bwd_fast<K, kZChunk, METHOD == kSFR, false>(
-                                yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
-                                zc0, acc);
-                        continue;
-                    }
-                    // per-voxel fallback (rare: overlapping or wide faces), kept rolled so
-                    // that it does not set the kernel's register count
-#pragma unroll 1
-                    for (int q = 0; q < kZChunk; ++q) {
-                        const int z = zc0 + q;
-                        if (z < nzv) {
-                            const Trap tr = sf_axial(an, bn, af, bf, (float)z, P.eps);
-                            float s = 0.0f;
-                            for_rows(tr, rows_total, [&](int j, float F) {
-                                const float *yr = yc0 + (int64_t)j * P.sino_row_stride;
-                                float rs = 0.0f;
-#pragma unroll
-                                for (int k = 0; k < K; ++k)
-                                    if (k < nc)
-                                        rs = fmaf(w[k], yr[k], rs);
-                                s = fmaf(F, rs, s);
-                            });
-                            if constexpr (METHOD == kSFR)
-                                s = fdiv(s, trap_area(tr));
-#pragma unroll
-                            for (int qq = 0; qq < kZChunk; ++qq)
-                                acc[qq] += qq == q ? s : 0.0f;
-                        }
-                    }
+                    sf_circ_gather<K, METHOD == kSFR>(P, yv, cs, nc, w, an, bn, af, bf, zc0,
+                                                     acc);
                 }
             } else if constexpr (METHOD == kSF && GEOM == kNonCirc) {
                 const float amp = sf_amp(V, P, xc, yc);
@@ -1340,82 +1458,12 @@ __global__ __launch_bounds__(256) void bwd_kernel(Params P, const ViewRec *__res
                     }
                 } else {
                     float al[K], be[K];
-                    bool walk = true;
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         al[k] = fmaf(bz[k], zb0, V.ddC);
                         be[k] = bz[k] * P.dz;
-                        walk = walk && !(k < nc && !(be[k] > 0.0f));
                     }
-                    if (CTP_BWD_FAST && walk) {
-                        // Footprint column k maps slice z onto rows [zeta_z, zeta_{z+1}],
-                        // zeta_f = al_k + be_k f, which tile the axis; the slice's gather is
-                        // R_k(zeta_{z+1}) - R_k(zeta_z), R_k the running integral of the column's
-                        // rows (clamped to the detector), so each row is loaded once.
-                        // all kZChunk + 1 boundaries are walked (clamped to the detector);
-                        // slices past the top one are dropped at write-out
-                        const float fr = (float)rows_total;
-                        const uint32_t rsb = (uint32_t)P.sino_row_stride * 4u;
-                        const float zc0f = (float)zc0;
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            if (k >= nc)
-                                break;
-                            const float a0 = fmaf(be[k], zc0f, al[k]);
-                            float RP = 0.0f, Dprev = 0.0f, rc = 0.0f;
-                            int jc = 0;
-                            uint32_t offb = 0;     // byte offset of row jc, cell cs + k, in the view
-                            auto row_at = [&](uint32_t ob) -> float {
-                                return *reinterpret_cast<const float *>(
-                                    reinterpret_cast<const char *>(yv) + ob);
-                            };
-#pragma unroll
-                            for (int f = 0; f <= kZChunk; ++f) {
-                                const float t = fminf(fmaxf(f == 0 ? a0 : fmaf((float)f, be[k], a0), 0.0f), fr);
-                                const int jt = min((int)t, rows_total - 1);
-                                if (f == 0) {
-                                    jc = jt;
-                                    offb = ((uint32_t)jc * (uint32_t)P.sino_row_stride +
-                                            (uint32_t)(cs + k)) * 4u;
-                                    rc = row_at(offb);
-                                }
-                                while (jc < jt) {
-                                    RP += rc;
-                                    ++jc;
-                                    offb += rsb;
-                                    rc = row_at(offb);
-                                }
-                                const float D = fmaf(t - (float)jc, rc, RP);
-                                if (f > 0) {
-                                    acc[f - 1] = fmaf(fx[k], D - Dprev, acc[f - 1]);
-                                    // keep the update here (see sf_bwd_fast)
-                                    asm volatile("" : "+v"(acc[f - 1]));
-                                }
-                                Dprev = D;
-                            }
-                        }
-                        continue;
-                    }
-#pragma unroll
-                    for (int q = 0; q < kZChunk; ++q) {
-                        const int z = zc0 + q;
-                        if (z < nzv) {
-                            float s = 0.0f;
-#pragma unroll
-                            for (int k = 0; k < K; ++k) {
-                                if (k < nc) {
-                                    const float zl = fmaf(be[k], (float)z, al[k]);
-                                    const float zh = zl + be[k];
-                                    float rs = 0.0f;
-                                    for_dd_rows(zl, zh, rows_total, [&](int j, float wz) {
-                                        rs = fmaf(wz, yc0[(int64_t)j * P.sino_row_stride + k], rs);
-                                    });
-                                    s = fmaf(fx[k], rs, s);
-                                }
-                            }
-                            acc[q] += s;
-                        }
-                    }
+                    dd_circ_gather<K>(P, yv, cs, nc, fx, al, be, zc0, acc);
                 }
             }
         }
