@@ -32,6 +32,9 @@
 #ifndef CTP_CVT_TRUNC
 #define CTP_CVT_TRUNC 0
 #endif
+#ifndef CTP_FWD_PAIRS
+#define CTP_FWD_PAIRS 1   // forward: fast columns two per wavefront in runs of 8 slices
+#endif
 #ifndef CTP_BWD_FAST
 #define CTP_BWD_FAST 1
 #endif
@@ -497,53 +500,62 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 // row j (j = -1 lands in the guard row below row 0) adds round(row value x w_k) to the NC cells.
 // INSIDE: the whole column projects into rows [0, R - 1) (checked per column, uniform), so the
 // row loops need no clamping to the row window.
-// Every lane runs five faces: when nz is not a multiple of 4, the last run continues past the
-// top slice with zero-valued slices on the same face lines (the callers' fast and inside tests
-// cover faces up to nz rounded up to a multiple of 4), which only adds zero row values.
-template <int K, int NC, bool NORM, bool INSIDE>
+// NS: slices per lane (4: one column per wavefront, 64 runs per 256 slices; 8: two columns per
+// wavefront, lanes 0-31 and 32-63 each taking 256 slices of their own column in runs of 8).
+// The column parameters may be uniform or per lane.  Every lane runs NS + 1 faces: when nz is
+// not a multiple of NS, the last run continues past the top slice with zero-valued slices on
+// the same face lines (the callers' fast and inside tests cover faces up to nz rounded up to a
+// multiple of 8), which only adds zero row values.
+template <int K, int NC, bool NORM, bool INSIDE, int NS>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
                                            const float (&w)[K], int *accs, int SW, int R,
                                            int lane)
 {
+    static_assert(NS == 4 || NS == 8, "runs of 4 or 8 slices");
     const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
     // every slice's trapezoid has the same area, the distance between consecutive face centres
     const float area = 0.5f * (bn + bf);
     const float inv_area = NORM ? fast_rcp(area) : 1.0f;
+    const int l = lane & (256 / NS - 1);
     for (int zb = 0; zb < nz; zb += 256) {
-        const int z0 = zb + 4 * lane;
+        const int z0 = zb + NS * l;
         if (z0 >= nz)
             break;
-        float v[4];
+        float v[NS];
         if ((nz & 3) == 0) {
-            const float4 v4 = *reinterpret_cast<const float4 *>(colp + z0);
-            v[0] = v4.x; v[1] = v4.y; v[2] = v4.z; v[3] = v4.w;
+#pragma unroll
+            for (int g = 0; g < NS; g += 4) {
+                const float4 v4 = z0 + g < nz ? *reinterpret_cast<const float4 *>(colp + z0 + g)
+                                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                v[g] = v4.x; v[g + 1] = v4.y; v[g + 2] = v4.z; v[g + 3] = v4.w;
+            }
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < NS; ++q)
                 v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
         }
-        // faces z0 .. z0 + 4 on the near and far lines, in rows relative to the run's base row
-        // edge (the subtraction is exact), so the face offsets within the run and the row
+        // faces z0 .. z0 + NS on the near and far lines, in rows relative to the run's base
+        // row edge (the subtraction is exact), so the face offsets within the run and the row
         // edges are accurate to a few ulps of the run's extent rather than of the row index
         const float z0f = (float)z0;
         const float an0 = fmaf(bn, z0f, an), af0 = fmaf(bf, z0f, af);
         const float base = floorf(fminf(an0, af0));
         const float an0r = an0 - base, af0r = af0 - base;
-        float p[5], qf[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            const float vn = f == 0 ? an0r : fmaf((float)f, bn, an0r);
-            const float vf = f == 0 ? af0r : fmaf((float)f, bf, af0r);
-            p[f] = fminf(vn, vf);
-            qf[f] = fmaxf(vn, vf);
-        }
+        // faces are formed as the walk reaches them (face f: [pf(f), qf(f)]), which keeps
+        // few of them live at once
+        auto pf = [&](int f) {
+            return f == 0 ? fminf(an0r, af0r) : fminf(fmaf((float)f, bn, an0r), fmaf((float)f, bf, af0r));
+        };
+        auto qff = [&](int f) {
+            return f == 0 ? fmaxf(an0r, af0r) : fmaxf(fmaf((float)f, bn, an0r), fmaf((float)f, bf, af0r));
+        };
         // skip runs entirely outside the row window
-        if (!INSIDE && (qf[4] < -base || base >= fR))
+        if (!INSIDE && (qff(NS) < -base || base >= fR))
             continue;
         if constexpr (NORM) {   // recon mode: each voxel's axial trapezoid normalised to unit area
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < NS; ++q)
                 v[q] *= inv_area;
         }
         // ft: the next row edge to close (relative; row base + ft - 1, row -1 being the guard
@@ -566,42 +578,47 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
         // Inside face q (or on voxel q's plateau above it), with u = t - q_q, e = max(u, 0),
         // d2 = e - u = max(q_q - t, 0) and d1 = w_q - d2 = min(t - p_q, w_q):
         //   local = v_q (d1^2 / (2 w_q) + e) - v_{q-1} d2^2 / (2 w_q)
+        float pc = pf(0), qc = qff(0);   // current face
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float wq = qf[q] - p[q];
+        for (int q = 0; q < NS; ++q) {
+            const float pn = pf(q + 1);
+            const float wq = qc - pc;
             const float h = 0.5f * fast_rcp(fmaxf(wq, 1e-30f));
-            const float fte = INSIDE ? ceilf(p[q + 1]) - 1.0f : ceilf(fminf(p[q + 1], lim1)) - 1.0f;
+            const float fte = INSIDE ? ceilf(pn) - 1.0f : ceilf(fminf(pn, lim1)) - 1.0f;
             if (q == 0) {   // no voxel below the run
                 while (ft <= fte) {
-                    const float u = ft - qf[0], e = fmaxf(u, 0.0f);
+                    const float u = ft - qc, e = fmaxf(u, 0.0f);
                     const float d1 = wq - (e - u);
                     emit(v[0] * fmaf(d1 * d1, h, e));
                 }
             } else {
                 const float nvh = -v[q - 1] * h;
                 while (ft <= fte) {
-                    const float u = ft - qf[q], e = fmaxf(u, 0.0f);
+                    const float u = ft - qc, e = fmaxf(u, 0.0f);
                     const float d2 = e - u, d1 = wq - d2;
                     emit(fmaf(v[q], fmaf(d1 * d1, h, e), (d2 * d2) * nvh));
                 }
             }
             cp = fmaf(-v[q], area, cp);   // S_{q+1} = S_q + v_q area
+            pc = pn;
+            qc = qff(q + 1);
         }
-        // above the run's top face: voxel 3's falling ramp over face 4
+        // above the run's top face: the last voxel's falling ramp over face NS
         {
-            const float h = 0.5f * fast_rcp(fmaxf(qf[4] - p[4], 1e-30f));
-            const float nvh = -v[3] * h;
-            const float fte = INSIDE ? floorf(qf[4]) + 1.0f : floorf(fminf(qf[4], limm1)) + 1.0f;
+            const float h = 0.5f * fast_rcp(fmaxf(qc - pc, 1e-30f));
+            const float nvh = -v[NS - 1] * h;
+            const float fte = INSIDE ? floorf(qc) + 1.0f : floorf(fminf(qc, limm1)) + 1.0f;
             while (ft <= fte) {
-                const float d2 = fmaxf(qf[4] - ft, 0.0f);
+                const float d2 = fmaxf(qc - ft, 0.0f);
                 emit((d2 * d2) * nvh);
             }
         }
     }
 }
 
-// Dispatch the SF run on the column's cell count (uniform across the wavefront).
-template <int K, bool NORM, bool INSIDE>
+// Dispatch the SF run on the column's (or column pair's) cell count, uniform across the
+// wavefront.
+template <int K, bool NORM, bool INSIDE, int NS>
 __device__ __forceinline__ void sf_fwd_run_nc(const float *__restrict__ colp, int nz, float an,
                                               float bn, float af, float bf,
                                               const float (&w)[K], int nc, int *accs, int SW,
@@ -609,15 +626,15 @@ __device__ __forceinline__ void sf_fwd_run_nc(const float *__restrict__ colp, in
 {
     if constexpr (K <= 4) {
         switch (nc) {
-        case 1: sf_fwd_run<K, 1, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
-        case 2: sf_fwd_run<K, 2, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
-        case 3: sf_fwd_run<K, (K >= 3 ? 3 : K), NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
-        default: sf_fwd_run<K, K, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 1: sf_fwd_run<K, 1, NORM, INSIDE, NS>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 2: sf_fwd_run<K, 2, NORM, INSIDE, NS>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        case 3: sf_fwd_run<K, (K >= 3 ? 3 : K), NORM, INSIDE, NS>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
+        default: sf_fwd_run<K, K, NORM, INSIDE, NS>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane); return;
         }
     } else {
         // wide footprints: all K cells (weights past nc are zero; the extra cells stay within
         // the strip row plus its padding)
-        sf_fwd_run<K, K, NORM, INSIDE>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane);
+        sf_fwd_run<K, K, NORM, INSIDE, NS>(colp, nz, an, bn, af, bf, w, accs, SW, R, lane);
     }
 }
 
@@ -844,16 +861,50 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                 // broadcast loop below reads the answers from two masks
                 uint64_t m_fast = 0, m_inside = 0;
                 if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
-                    // the runs cover faces up to nz rounded up to a multiple of 4
-                    const int nz4 = (P.nz + 3) & ~3;
-                    const bool fast = nc > 0 && sf_fast_ok(an, bn, af, bf, nz4);
-                    const float fnz = (float)nz4;
+                    // the runs cover faces up to nz rounded up to a multiple of 8
+                    const int nz8 = (P.nz + 7) & ~7;
+                    const bool fast = nc > 0 && sf_fast_ok(an, bn, af, bf, nz8);
+                    const float fnz = (float)nz8;
                     const bool inside = fast && fminf(an, af) >= 0.0f &&
                                         fmaxf(fmaf(bn, fnz, an), fmaf(bf, fnz, af)) < (float)(R - 1);
                     m_fast = __ballot(fast);
                     m_inside = __ballot(inside);
                 }
                 uint64_t m = __ballot(nc > 0);
+                if constexpr (GEOM != kFan2D && CTP_FWD_FAST && CTP_FWD_PAIRS) {
+                    // two fast columns at a time, lanes 0-31 on the first and 32-63 on the
+                    // second, each lane running 8 slices; the column parameters are moved to
+                    // the lanes with one LDS permute each
+                    uint64_t mp = m & m_fast;
+                    while (__popcll(mp) >= 2) {
+                        const int c1 = __ffsll((unsigned long long)mp) - 1;
+                        mp &= mp - 1ull;
+                        const int c2 = __ffsll((unsigned long long)mp) - 1;
+                        mp &= mp - 1ull;
+                        m &= ~((1ull << c1) | (1ull << c2));
+                        const int src = lane < 32 ? c1 : c2;
+                        const int p_nc = max(readlane_i(nc, c1), readlane_i(nc, c2));
+                        const bool p_inside = ((m_inside >> c1) & (m_inside >> c2) & 1ull) != 0;
+                        const int l_ix = __shfl(ix, src), l_iy = __shfl(iy, src);
+                        const int l_slot = __shfl(cs, src) - i_lo;
+                        float lw[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            lw[k] = __shfl(w[k], src);
+                        const float l_an = __shfl(an, src), l_bn = __shfl(bn, src);
+                        const float l_af = __shfl(af, src), l_bf = __shfl(bf, src);
+                        const float *colp = volb + ((int64_t)l_iy * P.nx + l_ix) * colstride;
+                        int *accs = acc + l_slot;
+                        if (p_inside)
+                            sf_fwd_run_nc<K, METHOD == kSFR, true, 8>(colp, P.nz, l_an, l_bn, l_af,
+                                                                      l_bf, lw, p_nc, accs, SW, R,
+                                                                      lane);
+                        else
+                            sf_fwd_run_nc<K, METHOD == kSFR, false, 8>(colp, P.nz, l_an, l_bn, l_af,
+                                                                       l_bf, lw, p_nc, accs, SW, R,
+                                                                       lane);
+                    }
+                }
                 while (m) {
                     const int c = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1ull;
@@ -870,11 +921,11 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
                         if ((m_fast >> c) & 1ull) {
                             if ((m_inside >> c) & 1ull)
-                                sf_fwd_run_nc<K, METHOD == kSFR, true>(colp, P.nz, s_an, s_bn, s_af,
+                                sf_fwd_run_nc<K, METHOD == kSFR, true, 4>(colp, P.nz, s_an, s_bn, s_af,
                                                                        s_bf, sw, s_nc, accs, SW, R,
                                                                        lane);
                             else
-                                sf_fwd_run_nc<K, METHOD == kSFR, false>(colp, P.nz, s_an, s_bn, s_af,
+                                sf_fwd_run_nc<K, METHOD == kSFR, false, 4>(colp, P.nz, s_an, s_bn, s_af,
                                                                         s_bf, sw, s_nc, accs, SW, R,
                                                                         lane);
                             continue;
