@@ -753,6 +753,12 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     extern __shared__ int acc_mem[];         // guard row, [R][kStripW + 1], kMaxCells of padding
     __shared__ int s_count, s_next;
     __shared__ unsigned short s_list[kListCap];
+    // 3D SF runs: each wavefront stages its tile's column parameters here (record field f of
+    // column c at s_colrec[wave][f][c]: voxel column index, strip slot, cell count, the axial
+    // lines an, bn, af, bf and the K cell weights), so that they do not occupy registers while
+    // the columns are walked
+    constexpr bool STAGE = METHOD != kDD && GEOM == kCirc && CTP_FWD_FAST;
+    __shared__ float s_colrec[STAGE ? kFwdThreads / 64 : 1][STAGE ? 7 + K : 1][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // XCD-aware order: work-group i runs on XCD i % 8; each XCD takes the strips
@@ -870,11 +876,23 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     m_fast = __ballot(fast);
                     m_inside = __ballot(inside);
                 }
+                float (*rec)[64] = s_colrec[STAGE ? wave : 0];
+                if constexpr (STAGE) {
+                    rec[0][lane] = __int_as_float(iy * P.nx + ix);
+                    rec[1][lane] = __int_as_float(cs - i_lo);
+                    rec[2][lane] = __int_as_float(nc);
+                    rec[3][lane] = an;
+                    rec[4][lane] = bn;
+                    rec[5][lane] = af;
+                    rec[6][lane] = bf;
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        rec[7 + k][lane] = w[k];
+                }
                 uint64_t m = __ballot(nc > 0);
-                if constexpr (GEOM != kFan2D && CTP_FWD_FAST && CTP_FWD_PAIRS) {
+                if constexpr (STAGE && CTP_FWD_PAIRS) {
                     // two fast columns at a time, lanes 0-31 on the first and 32-63 on the
-                    // second, each lane running 8 slices; the column parameters are moved to
-                    // the lanes with one LDS permute each
+                    // second, each lane running 8 slices and reading its column's record
                     uint64_t mp = m & m_fast;
                     while (__popcll(mp) >= 2) {
                         const int c1 = __ffsll((unsigned long long)mp) - 1;
@@ -883,17 +901,17 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                         mp &= mp - 1ull;
                         m &= ~((1ull << c1) | (1ull << c2));
                         const int src = lane < 32 ? c1 : c2;
-                        const int p_nc = max(readlane_i(nc, c1), readlane_i(nc, c2));
+                        const int p_nc = max(__float_as_int(rec[2][c1]), __float_as_int(rec[2][c2]));
                         const bool p_inside = ((m_inside >> c1) & (m_inside >> c2) & 1ull) != 0;
-                        const int l_ix = __shfl(ix, src), l_iy = __shfl(iy, src);
-                        const int l_slot = __shfl(cs, src) - i_lo;
+                        const int l_col = __float_as_int(rec[0][src]);
+                        const int l_slot = __float_as_int(rec[1][src]);
                         float lw[K];
 #pragma unroll
                         for (int k = 0; k < K; ++k)
-                            lw[k] = __shfl(w[k], src);
-                        const float l_an = __shfl(an, src), l_bn = __shfl(bn, src);
-                        const float l_af = __shfl(af, src), l_bf = __shfl(bf, src);
-                        const float *colp = volb + ((int64_t)l_iy * P.nx + l_ix) * colstride;
+                            lw[k] = rec[7 + k][src];
+                        const float l_an = rec[3][src], l_bn = rec[4][src];
+                        const float l_af = rec[5][src], l_bf = rec[6][src];
+                        const float *colp = volb + (int64_t)l_col * colstride;
                         int *accs = acc + l_slot;
                         if (p_inside)
                             sf_fwd_run_nc<K, METHOD == kSFR, true, 8>(colp, P.nz, l_an, l_bn, l_af,
@@ -908,15 +926,28 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                 while (m) {
                     const int c = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1ull;
-                    const int s_ix = readlane_i(ix, c), s_iy = readlane_i(iy, c);
-                    const int s_nc = readlane_i(nc, c), s_slot = readlane_i(cs, c) - i_lo;
+                    // column c's parameters as scalars (from the staged record or the lanes)
+                    auto col_i = [&](int f, int v) -> int {
+                        if constexpr (STAGE)
+                            return __builtin_amdgcn_readfirstlane(__float_as_int(rec[f][c]));
+                        else
+                            return readlane_i(v, c);
+                    };
+                    auto col_f = [&](int f, float v) -> float {
+                        if constexpr (STAGE)
+                            return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rec[f][c])));
+                        else
+                            return readlane_f(v, c);
+                    };
+                    const int s_col = col_i(0, iy * P.nx + ix);
+                    const int s_slot = col_i(1, cs - i_lo), s_nc = col_i(2, nc);
                     float sw[K];
 #pragma unroll
                     for (int k = 0; k < K; ++k)
-                        sw[k] = readlane_f(w[k], c);
-                    const float s_an = readlane_f(an, c), s_bn = readlane_f(bn, c);
-                    const float s_af = readlane_f(af, c), s_bf = readlane_f(bf, c);
-                    const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
+                        sw[k] = col_f(7 + k, w[k]);
+                    const float s_an = col_f(3, an), s_bn = col_f(4, bn);
+                    const float s_af = col_f(5, af), s_bf = col_f(6, bf);
+                    const float *colp = volb + (int64_t)s_col * colstride;
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
                         if ((m_fast >> c) & 1ull) {
