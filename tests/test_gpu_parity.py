@@ -261,6 +261,27 @@ def test_long_columns_and_strong_cone(torch_gpu, orc, method):
     assert rel_err(run_fwd(torch_gpu, plan2, x2), orc.forward(g2, x2, method=method)) <= TOL
 
 
+@pytest.mark.parametrize("nz", [36, 260])
+@pytest.mark.parametrize("det,method,mode", [("flat", "sf", "proj"), ("curved", "sf", "proj"),
+                                             ("flat", "dd", "proj"), ("flat", "sf", "recon")])
+def test_run_lengths(torch_gpu, orc, nz, det, method, mode):
+    """Columns whose length is a multiple of 4 but not of 8 (the forward's 8-slice runs of
+    paired columns end with zero-valued slices past the top one), in one pass (36) and in two
+    256-slice passes (260); the back projection's last z-chunk is partial in both."""
+    from paper_2503_16741_amd import ctproj
+    print(f"case nz={nz} {det}/{method}/{mode}", flush=True)
+    g = synth.Geometry(kind="cone", det=det, nx=10, ny=9, nz=nz, dx=1.0, dy=1.0,
+                       dz=65.0 / nz, nu=48, nv=360, du=0.5, dv=0.3, n_views=3,
+                       theta=np.array([0.2, 1.9, 4.0]), sad=200.0, sdd=300.0, z_ofst=0.7)
+    plan = ctproj.ctp_plan_create(g, method, mode)
+    x = synth.random_volume(g, seed=30)
+    assert rel_err(run_fwd(torch_gpu, plan, x),
+                   orc.forward(g, x, method=method, mode=mode)) <= TOL
+    y = synth.random_sinogram(g, seed=31)
+    assert rel_err(run_bwd(torch_gpu, plan, y),
+                   orc.adjoint(g, y, method=method, mode=mode)) <= TOL
+
+
 def test_empty_and_determinism(torch_gpu):
     from paper_2503_16741_amd import ctproj
     g = small_geom("cone", "flat", seed=14)
