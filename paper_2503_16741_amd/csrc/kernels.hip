@@ -642,26 +642,33 @@ __device__ __forceinline__ void sf_fwd_run_nc(const float *__restrict__ colp, in
 // [zeta_z, zeta_{z+1}] (rows, zeta_z = al_k + be_k z) tile the axis, so the run's integral up to
 // row edge t inside slice z is S_z + x_z (t - zeta_z) and row j gets C(j+1) - C(j) times the
 // column's transaxial fraction.  Same run-per-lane scheme as the SF path.
-template <int K>
+// NS: slices per lane as in sf_fwd_run (8: two columns per wavefront, parameters per lane).
+template <int K, int NS>
 __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int nz,
                                            const float (&al)[K], const float (&be)[K],
                                            const float (&fx)[K], int nc, int *accs,
                                            int SW, int R, int lane)
 {
-    // Every lane runs five boundaries; past the top slice (nz not a multiple of 4) the run
+    // Every lane runs NS + 1 boundaries; past the top slice (nz not a multiple of NS) the run
     // continues with zero-valued slices, which only adds zero row values.
+    static_assert(NS == 4 || NS == 8, "runs of 4 or 8 slices");
     const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
+    const int l = lane & (256 / NS - 1);
     for (int zb = 0; zb < nz; zb += 256) {
-        const int z0 = zb + 4 * lane;
+        const int z0 = zb + NS * l;
         if (z0 >= nz)
             break;
-        float v[4];
+        float v[NS];
         if ((nz & 3) == 0) {
-            const float4 v4 = *reinterpret_cast<const float4 *>(colp + z0);
-            v[0] = v4.x; v[1] = v4.y; v[2] = v4.z; v[3] = v4.w;
+#pragma unroll
+            for (int g = 0; g < NS; g += 4) {
+                const float4 v4 = z0 + g < nz ? *reinterpret_cast<const float4 *>(colp + z0 + g)
+                                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                v[g] = v4.x; v[g + 1] = v4.y; v[g + 2] = v4.z; v[g + 3] = v4.w;
+            }
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < NS; ++q)
                 v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
         }
         const float z0f = (float)z0;
@@ -672,12 +679,9 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
             // boundaries relative to the run's base row edge (exact subtraction)
             const float z00 = fmaf(be[k], z0f, al[k]);
             const float base = floorf(z00);
-            float zt[5];
-            zt[0] = z00 - base;
-#pragma unroll
-            for (int f = 1; f < 5; ++f)
-                zt[f] = fmaf((float)f, be[k], zt[0]);
-            if (zt[4] < -base || base >= fR)
+            const float zt0 = z00 - base;
+            auto zt = [&](int f) { return f == 0 ? zt0 : fmaf((float)f, be[k], zt0); };
+            if (zt(NS) < -base || base >= fR)
                 continue;
             // ft: the next row edge to close (relative; row base + ft - 1, row -1 being the
             // guard row), ap: that row's cell k; cp: C at the previous edge minus the prefix of
@@ -692,14 +696,17 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
                 ap += SW;
                 ft += 1.0f;
             };
+            float zc = zt0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float fte = ceilf(fminf(zt[q + 1], lim1)) - 1.0f;
+            for (int q = 0; q < NS; ++q) {
+                const float zn = zt(q + 1);
+                const float fte = ceilf(fminf(zn, lim1)) - 1.0f;
                 while (ft <= fte)
-                    emit(v[q] * (ft - zt[q]));
+                    emit(v[q] * (ft - zc));
                 cp = fmaf(-v[q], be[k], cp);     // every slice maps to be rows
+                zc = zn;
             }
-            const float fte = floorf(fminf(zt[4], limm1)) + 1.0f;
+            const float fte = floorf(fminf(zc, limm1)) + 1.0f;
             while (ft <= fte)
                 emit(0.0f);
         }
@@ -753,12 +760,14 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     extern __shared__ int acc_mem[];         // guard row, [R][kStripW + 1], kMaxCells of padding
     __shared__ int s_count, s_next;
     __shared__ unsigned short s_list[kListCap];
-    // 3D SF runs: each wavefront stages its tile's column parameters here (record field f of
-    // column c at s_colrec[wave][f][c]: voxel column index, strip slot, cell count, the axial
-    // lines an, bn, af, bf and the K cell weights), so that they do not occupy registers while
-    // the columns are walked
+    // 3D runs: each wavefront stages its tile's column parameters here (record field f of
+    // column c at s_colrec[wave][f][c]: voxel column index, strip slot, cell count, then SF: the
+    // axial lines an, bn, af, bf and the K cell weights; DD: the K overlap fractions and axial
+    // map scales), so that they do not occupy registers while the columns are walked
     constexpr bool STAGE = METHOD != kDD && GEOM == kCirc && CTP_FWD_FAST;
-    __shared__ float s_colrec[STAGE ? kFwdThreads / 64 : 1][STAGE ? 7 + K : 1][64];
+    constexpr bool STAGE_DD = METHOD == kDD && GEOM == kCirc && CTP_FWD_FAST;
+    constexpr int kRecFields = STAGE ? 7 + K : STAGE_DD ? 3 + 2 * K : 1;
+    __shared__ float s_colrec[STAGE || STAGE_DD ? kFwdThreads / 64 : 1][kRecFields][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // XCD-aware order: work-group i runs on XCD i % 8; each XCD takes the strips
@@ -876,7 +885,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     m_fast = __ballot(fast);
                     m_inside = __ballot(inside);
                 }
-                float (*rec)[64] = s_colrec[STAGE ? wave : 0];
+                float (*rec)[64] = s_colrec[STAGE || STAGE_DD ? wave : 0];
                 if constexpr (STAGE) {
                     rec[0][lane] = __int_as_float(iy * P.nx + ix);
                     rec[1][lane] = __int_as_float(cs - i_lo);
@@ -1053,23 +1062,76 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     }
                 }
                 uint64_t m = __ballot(nc > 0);
+                // 3D: stage the columns' parameters (column index, strip slot, cell count, and
+                // per footprint column the overlap fraction fx and the axial map scale bz) and
+                // walk the columns two per wavefront in runs of 8 slices, as in the SF loop
+                float (*rec)[64] = s_colrec[STAGE || STAGE_DD ? wave : 0];
+                if constexpr (STAGE_DD) {
+                    rec[0][lane] = __int_as_float(iy * P.nx + ix);
+                    rec[1][lane] = __int_as_float(cs - i_lo);
+                    rec[2][lane] = __int_as_float(nc);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        rec[3 + k][lane] = fx[k];
+                        rec[3 + K + k][lane] = bz[k];
+                    }
+                    if constexpr (CTP_FWD_PAIRS) {
+                        while (__popcll(m) >= 2) {
+                            const int c1 = __ffsll((unsigned long long)m) - 1;
+                            m &= m - 1ull;
+                            const int c2 = __ffsll((unsigned long long)m) - 1;
+                            m &= m - 1ull;
+                            const int src = lane < 32 ? c1 : c2;
+                            const int p_nc = max(__float_as_int(rec[2][c1]), __float_as_int(rec[2][c2]));
+                            float lfx[K], lal[K], lbe[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                lfx[k] = rec[3 + k][src];
+                                const float bk = rec[3 + K + k][src];
+                                lal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
+                                lbe[k] = bk * P.dz;
+                            }
+                            const float *colp = volb + (int64_t)__float_as_int(rec[0][src]) * colstride;
+                            int *accs = acc + __float_as_int(rec[1][src]);
+                            dd_fwd_run<K, 8>(colp, P.nz, lal, lbe, lfx, p_nc, accs, SW, R, lane);
+                        }
+                    }
+                }
                 while (m) {
                     const int c = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1ull;
-                    const int s_ix = readlane_i(ix, c), s_iy = readlane_i(iy, c);
-                    const int s_nc = readlane_i(nc, c), s_slot = readlane_i(cs, c) - i_lo;
                     float sfx[K], sal[K], sbe[K];
+                    int s_col, s_nc, s_slot;
+                    if constexpr (STAGE_DD) {
+                        auto col_i = [&](int f) -> int {
+                            return __builtin_amdgcn_readfirstlane(__float_as_int(rec[f][c]));
+                        };
+                        s_col = col_i(0);
+                        s_slot = col_i(1);
+                        s_nc = col_i(2);
 #pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        sfx[k] = readlane_f(fx[k], c);
-                        const float bk = readlane_f(bz[k], c);
-                        sal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
-                        sbe[k] = bk * P.dz;
+                        for (int k = 0; k < K; ++k) {
+                            sfx[k] = __int_as_float(col_i(3 + k));
+                            const float bk = __int_as_float(col_i(3 + K + k));
+                            sal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
+                            sbe[k] = bk * P.dz;
+                        }
+                    } else {
+                        s_col = readlane_i(iy * P.nx + ix, c);
+                        s_nc = readlane_i(nc, c);
+                        s_slot = readlane_i(cs, c) - i_lo;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            sfx[k] = readlane_f(fx[k], c);
+                            const float bk = readlane_f(bz[k], c);
+                            sal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
+                            sbe[k] = bk * P.dz;
+                        }
                     }
-                    const float *colp = volb + ((int64_t)s_iy * P.nx + s_ix) * colstride;
+                    const float *colp = volb + (int64_t)s_col * colstride;
                     int *accs = acc + s_slot;
                     if constexpr (GEOM != kFan2D && CTP_FWD_FAST) {
-                        dd_fwd_run<K>(colp, P.nz, sal, sbe, sfx, s_nc, accs, SW, R, lane);
+                        dd_fwd_run<K, 4>(colp, P.nz, sal, sbe, sfx, s_nc, accs, SW, R, lane);
                         continue;
                     }
                     for (int zb = zbeg; zb < zend; zb += 256) {
@@ -1414,8 +1476,11 @@ __device__ __forceinline__ void dd_circ_gather(const Params &P, const float *__r
 // Circular SF / recon-mode SF back projection is built for 8 wavefronts per SIMD (64 VGPRs; a
 // few spills outside the walk): measured faster than 7 at 69 VGPRs.  DD keeps the default (its
 // walk would spill).
+#ifndef CTP_BWD_SF_BLOCKS
+#define CTP_BWD_SF_BLOCKS 8
+#endif
 template <int GEOM, int METHOD>
-constexpr int bwd_min_blocks() { return GEOM == kCirc && METHOD != kDD ? 8 : 1; }
+constexpr int bwd_min_blocks() { return GEOM == kCirc && METHOD != kDD ? CTP_BWD_SF_BLOCKS : 1; }
 
 template <int GEOM, int DET, int METHOD, int K>
 __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_kernel(
