@@ -282,6 +282,23 @@ def test_run_lengths(torch_gpu, orc, nz, det, method, mode):
                    orc.adjoint(g, y, method=method, mode=mode)) <= TOL
 
 
+@pytest.mark.parametrize("du,nu", [(0.45, 100), (0.25, 160)])
+@pytest.mark.parametrize("method", ["sf", "dd"])
+def test_wide_footprints(torch_gpu, orc, du, nu, method):
+    """Fine detector columns: footprints of 5-8 and 9-16 cells (the kernels built for 8 and 16
+    cells per column, whose runs add every cell and whose staged column records are widest)."""
+    from paper_2503_16741_amd import ctproj
+    print(f"case du={du} {method}", flush=True)
+    g = synth.Geometry(kind="cone", det="flat", nx=14, ny=12, nz=40, dx=1.0, dy=1.0, dz=1.0,
+                       nu=nu, nv=150, du=du, dv=0.6, n_views=3,
+                       theta=np.array([0.3, 1.2, 2.6]), sad=120.0, sdd=240.0)
+    plan = ctproj.ctp_plan_create(g, method)
+    x = synth.random_volume(g, seed=40)
+    assert rel_err(run_fwd(torch_gpu, plan, x), orc.forward(g, x, method=method)) <= TOL
+    y = synth.random_sinogram(g, seed=41)
+    assert rel_err(run_bwd(torch_gpu, plan, y), orc.adjoint(g, y, method=method)) <= TOL
+
+
 def test_empty_and_determinism(torch_gpu):
     from paper_2503_16741_amd import ctproj
     g = small_geom("cone", "flat", seed=14)
