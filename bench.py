@@ -96,11 +96,14 @@ def summarize_traffic(fetch_csv, write_csv):
     f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
     out = {"source_hash": kernel_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
            "kernels": {}}
+    # the commands that produced the two CSVs (their output folders are the CSVs' folders,
+    # run name "t")
+    fdir, wdir = os.path.dirname(fetch_csv), os.path.dirname(write_csv)
     lines = ["# HBM traffic per launch, SF 256^3 x 360 views (rocprofv3 PMC)", "",
              "Commands (repository root, one MI355X):", "", "```",
-             "rocprofv3 --kernel-trace --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o t --output-format csv -- python3 bench.py --traffic-probe",
-             "rocprofv3 --kernel-trace --pmc WRITE_SIZE -d gpurun_out/pmc_write -o t --output-format csv -- python3 bench.py --traffic-probe",
-             "python3 bench.py --summarize-traffic gpurun_out/pmc_fetch/t_counter_collection.csv gpurun_out/pmc_write/t_counter_collection.csv",
+             f"rocprofv3 --kernel-trace --pmc FETCH_SIZE -d {fdir} -o t --output-format csv -- python3 bench.py --traffic-probe",
+             f"rocprofv3 --kernel-trace --pmc WRITE_SIZE -d {wdir} -o t --output-format csv -- python3 bench.py --traffic-probe",
+             f"python3 bench.py --summarize-traffic {fetch_csv} {write_csv}",
              "```", "",
              f"Calibration: a 512 MiB device copy in the same process reads FETCH_SIZE x {f_scale:.4f} and "
              f"writes WRITE_SIZE x {w_scale:.4f} of its known bytes; those factors scale every kernel below.",
