@@ -59,21 +59,27 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
-        L.orc_forward.restype = ctypes.c_int
-        L.orc_forward.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.c_void_p,
-                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
-        L.orc_adjoint.restype = ctypes.c_int
-        L.orc_adjoint.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.c_void_p,
-                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
-        L.orc_count.restype = ctypes.c_int
-        L.orc_count.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.c_int,
-                                ctypes.c_void_p, ctypes.c_void_p]
-        L.orc_num_threads.restype = ctypes.c_int
-        L.exr_integrals.restype = ctypes.c_int
-        L.exr_integrals.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 3
-        _lib = L
+        _lib = load(_LIB_PATH)
     return _lib
+
+
+def load(path: str):
+    """The oracle library at `path` with its entry points typed (the test suite also loads
+    deliberately broken builds of it, to show that the pins catch them)."""
+    L = ctypes.CDLL(path)
+    L.orc_forward.restype = ctypes.c_int
+    L.orc_forward.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_adjoint.restype = ctypes.c_int
+    L.orc_adjoint.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_count.restype = ctypes.c_int
+    L.orc_count.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.c_int,
+                            ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_num_threads.restype = ctypes.c_int
+    L.exr_integrals.restype = ctypes.c_int
+    L.exr_integrals.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 3
+    return L
 
 
 def _ptr(a: np.ndarray):

@@ -28,9 +28,14 @@
  *
  * Parity status: SF and DD forward/adjoint are pinned by the test suite (closed form of a
  * single voxel, parallel-beam exactness against exact path lengths, mass conservation,
- * adjoint identity, symmetries, reductions, brute-force ray integration, analytic
- * ellipsoids, empty/outside-FOV cases); recon mode by the closed-form sum of its weights,
- * the adjoint identity and filtered back projection of analytic discs and balls.
+ * adjoint identity and full-matrix gradient check, symmetries, reductions, brute-force ray
+ * integration, analytic ellipsoids, empty/outside-FOV cases); every pose and offset parameter
+ * of the geometry and the curved-detector mapping by closed-form projections of single voxels
+ * and by brute force with the parameter set; the distance-driven row mapping by the mirror
+ * symmetry of the curved detector.  A mutation test builds this file with one-line mistakes
+ * (flipped signs, dropped terms, wrong formulas) and requires a pin to fail for each.  Recon
+ * mode is pinned by the closed-form sum of its weights, the adjoint identity and filtered back
+ * projection of analytic discs and balls.
  */
 #include <math.h>
 #include <stdint.h>
