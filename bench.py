@@ -44,6 +44,10 @@ WORKLOAD = ("3D circular cone-beam SF-TT forward+back: 256^3 FP32 at 0.5 mm (20 
             "ellipsoids), 360 views/360 deg, flat 512x384 at 0.8 mm, SAD 785 mm, SDD 1200 mm")
 
 
+# --probe workloads: (scan constructor in synth, method)
+PROBES = {"sf_c2": ("cone_c2", "sf"), "dd_c2": ("cone_c2", "dd"), "sf_c4": ("noncirc_c4", "sf")}
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "plan.cpp", "engine.h"):
@@ -123,8 +127,25 @@ def summarize_traffic(fetch_csv, write_csv):
     print("\n".join(lines))
 
 
+def host_info():
+    """Host CPU model, logical CPUs and the threads the oracle uses."""
+    import oracle
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)), "oracle_threads": oracle.num_threads()}
+
+
 def cpu_baseline(geom, vol, n_views=128, n_vox=1500000):
-    """Time the FP64 oracle on a bounded sample of the same scan."""
+    """Time the FP64 oracle on a bounded sample of the same scan (about 12 s on 16 threads);
+    the full-scan runs (``--cpu-full``) are attached from their committed summary."""
     import numpy as np
     import oracle
     from paper_2503_16741_amd import synth
@@ -140,18 +161,71 @@ def cpu_baseline(geom, vol, n_views=128, n_vox=1500000):
     t3 = time.perf_counter()
     updates = n_views * geom.n_vox + n_vox * geom.n_views
     secs = (t1 - t0) + (t3 - t2)
-    return {"value": updates / secs / 1e9, "unit": "GUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle: SF forward of the full 256^3 phantom for {n_views} of 360 "
-                      f"views + SF adjoint at {n_vox} random voxels over all 360 views "
-                      f"({updates:.3e} voxel-view updates in {secs:.1f} s)"}
+    hi = host_info()
+    out = {"value": updates / secs / 1e9, "unit": "GUPS", "cores": hi["oracle_threads"],
+           "kind": "oracle", "cpu_model": hi["cpu_model"], "nproc": hi["nproc"],
+           "sample": f"FP64 oracle: SF forward of the full 256^3 phantom for {n_views} of 360 "
+                     f"views + SF adjoint at {n_vox} random voxels over all 360 views "
+                     f"({updates:.3e} voxel-view updates in {secs:.1f} s)"}
+    try:
+        with open(os.path.join(ROOT, "profiles", "cpu_oracle_full.json")) as fh:
+            out["full_runs"] = json.load(fh)
+    except (OSError, ValueError):
+        pass
+    return out
 
 
-def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, seed=0):
+def cpu_full():
+    """The unmodified FP64 oracle over whole scans on all host threads: 256^3 x 360 views SF and
+    DD, each direction once, and the 2D 128^2 x 180-view scan in full.  Writes
+    profiles/cpu_oracle_full.json and .md."""
+    import numpy as np
+    import oracle
+    from paper_2503_16741_amd import synth
+    hi = host_info()
+    runs = []
+    for name, g in (("256^3 x 360 views, flat 512x384 (cone)", synth.cone_c2()),
+                    ("128^2 x 180 views, flat 256 (2D fan)", synth.fan2d_c1())):
+        vol = synth.phantom(g, seed=0)
+        ys = synth.random_sinogram(g, seed=1)
+        vv = float(g.n_vox) * g.n_views
+        for method in ("sf", "dd"):
+            t0 = time.perf_counter()
+            oracle.forward(g, vol, method=method)
+            t1 = time.perf_counter()
+            oracle.adjoint(g, ys, method=method)
+            t2 = time.perf_counter()
+            r = {"scan": name, "method": method, "forward_s": round(t1 - t0, 3),
+                 "adjoint_s": round(t2 - t1, 3), "voxel_views": vv,
+                 "gups_pair": round(2 * vv / (t2 - t0) / 1e9, 4)}
+            print(f"[cpu-full] {r}", file=sys.stderr, flush=True)
+            runs.append(r)
+    res = dict(hi, runs=runs)
+    with open(os.path.join(ROOT, "profiles", "cpu_oracle_full.json"), "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = ["# FP64 CPU oracle on whole scans", "", "Command (repository root, GPU box host):", "",
+             "```", "python3 bench.py --cpu-full", "```", "",
+             f"Host: {hi['cpu_model']}; {hi['nproc']} logical CPUs, {hi['affinity']} in this "
+             f"process's affinity mask; the oracle ran {hi['oracle_threads']} OpenMP threads "
+             "(forward parallel over views, adjoint over voxels).", "",
+             "| scan | method | forward s | adjoint s | GUPS (pair) |", "|---|---|---|---|---|"]
+    for r in runs:
+        lines.append(f"| {r['scan']} | {r['method'].upper()} | {r['forward_s']} | "
+                     f"{r['adjoint_s']} | {r['gups_pair']} |")
+    with open(os.path.join(ROOT, "profiles", "cpu_oracle_full.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(res), flush=True)
+
+
+def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, seed=0,
+                  burst=128, emit=True):
     """Serving under Poisson arrivals: requests drawn uniformly from the ladder (2D fan 256^2 and
     3D cone 128^3 / 256^3 / 384^3, 400 views) x {forward, back} x {FP32, BF16}, submitted to the
     serving engine at `load` times the rate one device sustains when the requests run one after
-    another; latency = completion - submission on the server's clock."""
+    another; latency = completion - submission on the server's clock.  Also a saturated burst
+    (`burst` requests of the same mix submitted at once): its throughput against the serial one
+    shows what overlapping calls on several streams gains.  Returns the result dict (and prints
+    it as a JSON line when `emit`)."""
     import queue
     import threading
     import numpy as np
@@ -195,9 +269,31 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, seed=0):
     print(f"[serving] mean service time alone {mean_svc:.2f} ms -> {capacity:.1f} req/s; "
           f"alone throughput {alone_gups:.1f} GUPS", file=sys.stderr, flush=True)
 
-    srv = ctproj.Server(int(arena_gb * (1 << 30)), n_slots=n_slots, max_batch=max_batch)
+    srv = ctproj.Server(int(arena_gb * (1 << 30)), n_slots=n_slots, max_batch=max_batch,
+                        age_cap_s=age_cap_ms * 1e-3)
     results = []
     rng = np.random.default_rng(seed + 1)
+
+    # saturated burst: everything queued at once; throughput = work / makespan
+    picks = rng.integers(len(classes), size=burst)
+    torch.cuda.synchronize()
+    tickets = [(srv.submit(plans[classes[int(k)][0]], classes[int(k)][1], inputs[classes[int(k)]]),
+                classes[int(k)]) for k in picks]
+    infos = []
+    for t, c in tickets:
+        srv.wait(t)
+        infos.append((c, srv.info(t)))
+    for t, _ in tickets:
+        srv.release(t)
+    span = (max(i["done_ns"] for _, i in infos) - min(i["submit_ns"] for _, i in infos)) * 1e-9
+    burst_gups = sum(vv[c] for c, _ in infos) / span / 1e9
+    serial_ms = sum(svc[c] for c, _ in infos)
+    burst_res = {"requests": int(burst), "gups": round(burst_gups, 2),
+                 "makespan_ms": round(span * 1e3, 2), "serial_ms": round(serial_ms, 2),
+                 "mean_batch": round(float(np.mean([i["batch"] for _, i in infos])), 3)}
+    print(f"[serving] burst of {burst}: {burst_res['gups']} GUPS (serial {alone_gups:.1f}), "
+          f"makespan {burst_res['makespan_ms']} ms vs serial {burst_res['serial_ms']} ms",
+          file=sys.stderr, flush=True)
     for load in loads:
         lam = load * capacity
         gaps = rng.exponential(1.0 / lam, size=int(lam * seconds * 2) + 16)
@@ -239,9 +335,14 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, seed=0):
                 per[n] = {"n": int(len(l)), "p50_ms": round(float(np.percentile(l, 50)), 3),
                           "p99_ms": round(float(np.percentile(l, 99)), 3)}
         batches = np.array([i["batch"] for _, i in records])
+        # slowdown: latency over the request's own service time alone
+        slow = np.array([(i["done_ns"] - i["submit_ns"]) * 1e-6 / svc[c] for c, i in records])
         r = {"load": load, "lambda_per_s": round(lam, 2), "n_requests": int(len(records)),
-             "gups": round(gups, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+             "gups": round(gups, 2), "offered_gups": round(load * alone_gups, 2),
+             "p50_ms": round(float(np.percentile(lat, 50)), 3),
              "p99_ms": round(float(np.percentile(lat, 99)), 3),
+             "slowdown_p50": round(float(np.percentile(slow, 50)), 2),
+             "slowdown_p99": round(float(np.percentile(slow, 99)), 2),
              "mean_batch": round(float(batches.mean()), 3), "per_class": per}
         print(f"[serving] load {load}: {r['n_requests']} requests, {r['gups']} GUPS, "
               f"p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms", file=sys.stderr, flush=True)
@@ -257,17 +358,20 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, seed=0):
                                   "128^3 / 256^3 / 384^3 at 0.4 mm (400 views, flat 640x480 at "
                                   "0.6 mm), FP32 or BF16, 50/50 forward/back",
                       "arena_gb": arena_gb, "n_slots": n_slots, "max_batch": max_batch,
-                      "seconds_per_load": seconds},
+                      "age_cap_ms": age_cap_ms, "seconds_per_load": seconds},
            "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
            "alone": {"gups": round(alone_gups, 2), "mean_service_ms": round(mean_svc, 3),
                      "capacity_req_per_s": round(capacity, 2),
                      "service_ms": {f"{c[0]}/{c[1]}/{str(c[2]).split('.')[-1]}": round(v, 3)
                                     for c, v in svc.items()}},
            "loads": results,
+           "burst": burst_res,
            "server": {"calls": st["calls"], "max_running": st["max_running"],
                       "max_batch_seen": st["max_batch_seen"],
                       "arena_peak_gb": round(st["arena_peak"] / (1 << 30), 3)}}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -280,9 +384,14 @@ def main():
     ap.add_argument("--no-recon", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the FP64 oracle over whole scans (minutes) and write its summary")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB device copy, one SF forward and one SF back projection "
                          "(for FETCH_SIZE / WRITE_SIZE counter runs) and exit")
+    ap.add_argument("--probe", choices=sorted(PROBES),
+                    help="like --traffic-probe for another workload: sf_c2 / dd_c2 (256^3 x 360 "
+                         "views), sf_c4 (non-circular 384^3 x 500 views with pose jitter)")
     ap.add_argument("--serving", action="store_true",
                     help="run the serving benchmark (Poisson arrivals of mixed requests) instead")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
@@ -290,9 +399,15 @@ def main():
     ap.add_argument("--serving-arena-gb", type=float, default=32.0)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-max-batch", type=int, default=8)
+    ap.add_argument("--serving-age-cap-ms", type=float, default=50.0)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave the serving field out of the default run")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
+        return
+    if args.cpu_full:
+        cpu_full()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -302,7 +417,8 @@ def main():
 
     if args.serving:
         serving_bench(args.serving_seconds, [float(v) for v in args.serving_loads.split(",")],
-                      args.serving_arena_gb, args.serving_slots, args.serving_max_batch)
+                      args.serving_arena_gb, args.serving_slots, args.serving_max_batch,
+                      args.serving_age_cap_ms)
         return
 
     import numpy as np
@@ -342,9 +458,18 @@ def main():
               f"wall {wall * 1e3 / steps:.3f} ms/step", file=sys.stderr, flush=True)
         return wall, fwd, bwd, pair
 
-    plan = ctproj.ctp_plan_create(g, "sf")
-    if args.traffic_probe:
+    if args.traffic_probe or args.probe:
         # a plain copy of known size calibrates the counters; then one call of each kernel
+        name = args.probe or "sf_c2"
+        scan, method = PROBES[name]
+        gp = g if scan == "cone_c2" else getattr(synth, scan)()
+        if gp is not g:
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(5)
+            vol = torch.rand(gp.vol_shape, generator=gen, device=dev)
+            sino = torch.empty(gp.sino_shape, dtype=torch.float32, device=dev)
+            back = torch.empty_like(vol)
+        plan = ctproj.ctp_plan_create(gp, method)
         src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -352,8 +477,9 @@ def main():
         ctproj.ctp_project(plan, vol, sino)
         ctproj.ctp_backproject(plan, sino, back)
         torch.cuda.synchronize()
-        print(json.dumps({"traffic_probe": True, "copy_bytes": src.numel() * 4}), flush=True)
+        print(json.dumps({"probe": name, "copy_bytes": src.numel() * 4}), flush=True)
         return
+    plan = ctproj.ctp_plan_create(g, "sf")
     wall, fwd, bwd, pair = run(plan, args.steps, args.warmup, "SF")
     vv = float(g.n_vox) * g.n_views
     value = 2.0 * vv * args.steps / wall / 1e9
@@ -557,6 +683,22 @@ def main():
         print(f"[bench] FDK: ramp {ramp.mean():.3f} ms, recon back projection {bpr.mean():.3f} ms",
               file=sys.stderr, flush=True)
         plan_r.close()
+
+    if not args.no_serving:
+        # the serving engine under Poisson arrivals of mixed requests, 20 s per load
+        del vol, sino, back
+        torch.cuda.empty_cache()
+        sv = serving_bench(20.0, [0.7, 0.9], args.serving_arena_gb, args.serving_slots,
+                           args.serving_max_batch, args.serving_age_cap_ms, emit=False)
+        out["serving"] = {
+            "workload": sv["config"]["workload"], "seconds_per_load": 20.0,
+            "n_slots": args.serving_slots, "max_batch": args.serving_max_batch,
+            "age_cap_ms": args.serving_age_cap_ms,
+            "serial": sv["alone"]["gups"], "mean_service_ms": sv["alone"]["mean_service_ms"],
+            "burst": sv["burst"],
+            "loads": [{k: r[k] for k in ("load", "n_requests", "gups", "offered_gups", "p50_ms",
+                                         "p99_ms", "slowdown_p50", "slowdown_p99",
+                                         "mean_batch", "per_class")} for r in sv["loads"]]}
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -43,7 +43,8 @@ typedef enum {
     CTP_EUNSUPPORTED = -2,  /* valid request that this build does not implement */
     CTP_ENOMEM = -3,        /* device or host allocation failed */
     CTP_EDEVICE = -4,       /* HIP runtime / launch failure */
-    CTP_ETIMEOUT = -5       /* a wait ended before the work was done (ctserve.h) */
+    CTP_ETIMEOUT = -5,      /* a wait ended before the work was done (ctserve.h) */
+    CTP_ECANCELED = -6      /* the request was cancelled before it ran (ctserve.h) */
 } ctp_status;
 
 /* Scan kinds (Section 2.2). */

@@ -11,11 +11,16 @@
  *     top, freed when the call completes).  A request is admitted only when those blocks fit;
  *     until then it waits in the queue.  Outputs stay resident in the arena until released, so
  *     a client that holds results can keep later requests waiting (a wait then times out).
- *   - Batching.  When a slot is free the oldest queued request is admitted together with the
- *     later queued requests that share its plan, direction and storage types (at most
- *     max_batch; the paper's batched, channelled tensors, Section 1 and 2.4: one plan serves the
- *     whole batch).  If the merged call does not fit, fewer requests are merged; the oldest
- *     request is always the next to run (first come, first served).
+ *   - Order.  When a slot is free the server picks the head of the next call: requests that
+ *     have waited at least age_cap_us come first, oldest first; the others follow in order of
+ *     their work (voxel-view updates: n_vox x n_views of the plan), smallest first, so short
+ *     requests are not held behind long ones.  A head whose call does not fit in the arena is
+ *     passed over in favour of the next one unless it has reached the age cap, in which case
+ *     nothing else starts until it fits.  age_cap_us = 0 gives strict first come, first served.
+ *   - Batching.  The head is admitted together with the other queued requests that share its
+ *     plan, direction and storage types (at most max_batch, in arrival order; the paper's
+ *     batched, channelled tensors, Section 1 and 2.4: one plan serves the whole batch).  If the
+ *     merged call does not fit, fewer requests are merged.
  *   - Overlap.  Each slot owns a HIP stream; up to n_slots calls run concurrently.
  *
  * Results are those of ctp_project / ctp_backproject with batch = the merged count.  Every
@@ -23,8 +28,9 @@
  * projector's fixed-point scale is chosen per item, the back projector is a per-voxel gather),
  * so a request gets the same bits alone and in the mix.
  *
- * The server runs one host thread of its own, which polls the slots' completion events while
- * calls are in flight (one busy host core) and sleeps when the server is idle.
+ * The server runs one host thread of its own.  While calls are in flight it looks at their
+ * completion events every 50 us (a timed sleep that a submission, release or cancellation ends
+ * early); when the server is idle it sleeps until the next submission.
  * All functions return a ctp_status; ctp_last_error() holds the detail.
  */
 #ifndef CTSERVE_H
@@ -44,6 +50,8 @@ typedef struct {
     size_t arena_bytes;   /* the HBM budget */
     int32_t n_slots;      /* concurrent calls (streams), 1..16 */
     int32_t max_batch;    /* most requests merged into one call, 1..1024 */
+    int64_t age_cap_us;   /* wait after which a request is served in arrival order (>= 0;
+                             0 = strict first come, first served) */
 } ctp_server_config;
 
 /* Host-clock times (steady clock, ns) and placement of one request. */
@@ -57,6 +65,7 @@ typedef struct {
 
 typedef struct {
     int64_t submitted, completed, failed, calls;
+    int64_t cancelled;    /* requests removed from the queue by ctp_server_cancel */
     int32_t max_running;  /* most calls in flight at once */
     int32_t max_batch_seen;
     size_t arena_peak;    /* most arena bytes in use at once */
@@ -80,8 +89,8 @@ ctp_status ctp_server_submit(ctp_server *srv, const ctp_plan *plan, ctp_directio
 /* Wait until the request is done (timeout_us < 0: no limit).  On success *result (if not NULL)
  * is the device address of its output inside the arena, complete and valid until released.
  * Errors: CTP_EINVAL (unknown or released ticket), CTP_ETIMEOUT (not done within timeout_us;
- * the request goes on), or the status of its failed call (CTP_EINVAL / CTP_EDEVICE, with the
- * call's message). */
+ * the request goes on), CTP_ECANCELED (cancelled), or the status of its failed call
+ * (CTP_EINVAL / CTP_EDEVICE, with the call's message). */
 ctp_status ctp_server_wait(ctp_server *srv, uint64_t ticket, int64_t timeout_us, void **result);
 
 /* Non-blocking: *done = 1 and *result set when complete, else *done = 0. */
@@ -89,6 +98,11 @@ ctp_status ctp_server_query(ctp_server *srv, uint64_t ticket, int *done, void **
 
 /* Times and placement of a request (valid until it is released). */
 ctp_status ctp_server_info(ctp_server *srv, uint64_t ticket, ctp_request_info *info);
+
+/* Remove a queued request (one whose call has not been admitted).  Its wait and query then
+ * report CTP_ECANCELED, and the ticket must still be released.  Errors: CTP_EINVAL for an
+ * unknown or released ticket and for a request that is already running or finished. */
+ctp_status ctp_server_cancel(ctp_server *srv, uint64_t ticket);
 
 /* Give the request's output back to the arena.  `consumer` is the stream on which the caller's
  * last use of the output was enqueued: the memory is reused only after that work has run.

@@ -17,6 +17,9 @@ namespace ctp {
 ctp_status set_error(ctp_status st, const std::string &msg);
 void clear_error();
 int plan_device(const ctp_plan *plan);
+// Voxel-view updates of one batch item of a call with this plan (n_vox x n_views): the serving
+// engine's estimate of a request's work.
+double plan_work(const ctp_plan *plan);
 
 enum Geom : int { kFan2D = 0, kCirc = 1, kNonCirc = 2 };
 enum Det : int { kFlat = 0, kCurved = 1 };

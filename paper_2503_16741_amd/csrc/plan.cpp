@@ -116,6 +116,11 @@ namespace ctp {
 ctp_status set_error(ctp_status st, const std::string &msg) { return fail(st, msg); }
 void clear_error() { g_last_error.clear(); }
 int plan_device(const ctp_plan *plan) { return plan->device; }
+double plan_work(const ctp_plan *plan)
+{
+    const ctp_geometry_desc &g = plan->g;
+    return (double)g.nx * g.ny * (g.kind == CTP_FAN2D ? 1 : g.nz) * g.n_views;
+}
 }  // namespace ctp
 
 extern "C" {
@@ -129,6 +134,7 @@ const char *ctp_status_string(ctp_status s)
     case CTP_ENOMEM: return "out of memory";
     case CTP_EDEVICE: return "device error";
     case CTP_ETIMEOUT: return "timed out";
+    case CTP_ECANCELED: return "cancelled";
     }
     return "unknown status";
 }
@@ -530,16 +536,15 @@ ctp_status finish(hipError_t e, hipStream_t stream, const char *what)
 
 }  // namespace
 
-ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
-                       ctp_dtype sino_dtype, int64_t batch, int accumulate, void *workspace,
-                       size_t workspace_bytes, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// The forward projection into a validated workspace (prepare_call has run).
+ctp_status project_into(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
+                        ctp_dtype sino_dtype, int64_t batch, int accumulate, void *workspace,
+                        const ctp::Params &p, hipStream_t stream)
 {
-    g_last_error.clear();
-    ctp::Params p;
-    ctp_status st = prepare_call(plan, vol, sino, vol_dtype, sino_dtype, batch, workspace,
-                                 workspace_bytes, CTP_FORWARD, p);
-    if (st != CTP_OK)
-        return st;
     const FwdWs w = fwd_ws_layout(plan, batch, sino_dtype);
     char *ws = static_cast<char *>(workspace);
     float *qscale = reinterpret_cast<float *>(ws);
@@ -562,6 +567,24 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
         e = ctp::launch_store_convert(out, sino, (int)sino_dtype, (int64_t)(sb / 4), accumulate, stream);
     }
     return finish(e, stream, "forward projection");
+}
+
+}  // namespace
+
+extern "C" {
+
+ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
+                       ctp_dtype sino_dtype, int64_t batch, int accumulate, void *workspace,
+                       size_t workspace_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    ctp::Params p;
+    ctp_status st = prepare_call(plan, vol, sino, vol_dtype, sino_dtype, batch, workspace,
+                                 workspace_bytes, CTP_FORWARD, p);
+    if (st != CTP_OK)
+        return st;
+    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, accumulate, workspace, p,
+                        stream);
 }
 
 ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *vol,

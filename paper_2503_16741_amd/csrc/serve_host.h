@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <algorithm>
 #include <deque>
 #include <iterator>
 #include <map>
@@ -136,21 +137,50 @@ struct BatchKey {
     }
 };
 
-// Positions in `queue` (oldest first) of the requests merged with the oldest one: the head and
-// then, in arrival order, later requests with the same key, at most max_batch in all.  The
-// head is always served first (first come, first served); requests of other keys keep their
-// places.  `key_of` maps a queue element to its BatchKey.
+// Positions in `queue` (oldest first) of the requests merged into a call headed by
+// queue[head]: the head, then, in arrival order, the other queued requests with the same key,
+// at most max_batch in all.  `key_of` maps a queue element to its BatchKey.
 template <typename T, typename KeyOf>
-std::vector<size_t> batch_candidates(const std::deque<T> &queue, int max_batch, KeyOf key_of)
+std::vector<size_t> batch_candidates(const std::deque<T> &queue, size_t head, int max_batch,
+                                     KeyOf key_of)
 {
     std::vector<size_t> pos;
-    if (queue.empty() || max_batch < 1)
+    if (head >= queue.size() || max_batch < 1)
         return pos;
-    const BatchKey head = key_of(queue.front());
+    const BatchKey hk = key_of(queue[head]);
+    pos.push_back(head);
     for (size_t i = 0; i < queue.size() && (int)pos.size() < max_batch; ++i)
-        if (key_of(queue[i]) == head)
+        if (i != head && key_of(queue[i]) == hk)
             pos.push_back(i);
     return pos;
+}
+
+// Order in which queued requests are tried as the head of the next call.  Requests that have
+// waited at least age_cap_ns ("aged") come first, oldest first; the others follow cheapest first
+// (smallest predicted work), ties in arrival order, so that short requests are not held behind
+// long ones while no request waits longer than the cap before it is next in line.  With
+// age_cap_ns <= 0 every request counts as aged: strict first come, first served.  `info` maps a
+// queue element to {work, submit time}.  *n_aged receives the number of aged requests (they
+// are the first *n_aged positions).
+template <typename T, typename Info>
+std::vector<size_t> head_order(const std::deque<T> &queue, int64_t now_ns, int64_t age_cap_ns,
+                               Info info, size_t *n_aged)
+{
+    std::vector<size_t> aged, young;
+    for (size_t i = 0; i < queue.size(); ++i) {
+        const auto wi = info(queue[i]);
+        if (age_cap_ns <= 0 || now_ns - wi.second >= age_cap_ns)
+            aged.push_back(i);
+        else
+            young.push_back(i);
+    }
+    std::stable_sort(young.begin(), young.end(), [&](size_t a, size_t b) {
+        return info(queue[a]).first < info(queue[b]).first;
+    });
+    if (n_aged)
+        *n_aged = aged.size();
+    aged.insert(aged.end(), young.begin(), young.end());
+    return aged;
 }
 
 }  // namespace ctp

@@ -40,6 +40,7 @@ struct Request {
     const void *input = nullptr;
     ctp_dtype in_dt = CTP_F32, out_dt = CTP_F32;
     size_t in_bytes = 0, out_bytes = 0;
+    double work = 0.0;                     // voxel-view updates: the cost estimate
     hipEvent_t ready = nullptr;            // recorded on the producer's stream at submit
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     enum State { kQueued, kRunning, kDone, kFailed } state = kQueued;
@@ -79,10 +80,14 @@ ctp_status call_workspace(const Request *r, int64_t n, size_t *bytes)
 
 }  // namespace
 
+// Interval at which the server thread looks at the completion events of running calls.
+constexpr int kPollUs = 50;
+
 struct ctp_server {
     int device = -1;
     char *arena = nullptr;
     int max_batch = 1;
+    int64_t age_cap_ns = 0;             // 0: strict first come, first served
     std::vector<Slot> slots;
 
     std::mutex mu;
@@ -180,12 +185,31 @@ struct ctp_server {
         return progress;
     }
 
-    // Take the oldest request and the queued requests that may join its call, reserve their
-    // memory and a slot.  Returns an empty pointer if the oldest request does not fit now.
+    // Choose the next call: try heads in ctp::head_order (requests older than the age cap
+    // first, oldest first; then the rest cheapest first), each with the queued requests that
+    // may join its call, and reserve the memory and the slot of the first that fits.  A young
+    // head that does not fit is passed over; an aged one is not (the memory that frees up is
+    // kept for it), so no request waits behind later ones for longer than the cap.  Returns an
+    // empty pointer if nothing may start now.
     std::shared_ptr<Batch> admit(int slot)
     {
-        std::vector<size_t> pos = ctp::batch_candidates(queue, max_batch, key_of);
-        const Request *head = queue.front();
+        size_t n_aged = 0;
+        const std::vector<size_t> order = ctp::head_order(
+            queue, now_ns(), age_cap_ns,
+            [](const Request *r) { return std::make_pair(r->work, r->t_submit); }, &n_aged);
+        for (size_t k = 0; k < order.size(); ++k) {
+            std::shared_ptr<Batch> b = try_admit(order[k], slot);
+            if (b || k < n_aged)
+                return b;
+        }
+        return nullptr;
+    }
+
+    // Reserve a call headed by queue[head_pos] with as many of its batch candidates as fit.
+    std::shared_ptr<Batch> try_admit(size_t head_pos, int slot)
+    {
+        std::vector<size_t> pos = ctp::batch_candidates(queue, head_pos, max_batch, key_of);
+        const Request *head = queue[head_pos];
         for (int64_t n = (int64_t)pos.size(); n >= 1; --n) {
             size_t ws = 0;
             if (call_workspace(head, n, &ws) != CTP_OK)
@@ -211,12 +235,15 @@ struct ctp_server {
             b->out_item = head->out_bytes;
             b->staging = staging;
             b->ws_bytes = ws;
-            // remove the chosen requests from the queue (back to front keeps positions valid)
+            // remove the chosen requests from the queue (highest position first keeps the
+            // others valid)
             std::vector<Request *> items;
             for (int64_t i = 0; i < n; ++i)
                 items.push_back(queue[pos[(size_t)i]]);
-            for (int64_t i = n - 1; i >= 0; --i)
-                queue.erase(queue.begin() + (std::ptrdiff_t)pos[(size_t)i]);
+            std::vector<size_t> del(pos.begin(), pos.begin() + n);
+            std::sort(del.begin(), del.end());
+            for (auto it = del.rbegin(); it != del.rend(); ++it)
+                queue.erase(queue.begin() + (std::ptrdiff_t)*it);
             const int64_t t = now_ns();
             for (int64_t i = 0; i < n; ++i) {
                 Request *r = items[(size_t)i];
@@ -335,10 +362,9 @@ struct ctp_server {
                 return;
             }
             if (busy) {
-                // calls in flight: poll their events
-                lk.unlock();
-                std::this_thread::yield();
-                lk.lock();
+                // calls in flight: look at their events again after a short sleep, or at once
+                // when a request arrives, is released or cancelled
+                wake.wait_for(lk, std::chrono::microseconds(kPollUs));
             } else {
                 wake.wait(lk);
             }
@@ -377,6 +403,8 @@ ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out)
         return ctp::set_error(CTP_EINVAL, "n_slots must be in 1..16");
     if (cfg->max_batch < 1 || cfg->max_batch > 1024)
         return ctp::set_error(CTP_EINVAL, "max_batch must be in 1..1024");
+    if (cfg->age_cap_us < 0)
+        return ctp::set_error(CTP_EINVAL, "age_cap_us must be >= 0");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess)
         return ctp::set_error(CTP_EDEVICE, "no HIP device");
@@ -386,6 +414,7 @@ ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out)
     s->device = dev;
     s->arena = static_cast<char *>(cfg->arena);
     s->max_batch = cfg->max_batch;
+    s->age_cap_ns = cfg->age_cap_us * 1000;
     s->alloc.reset(cfg->arena_bytes);
     s->slots.resize((size_t)cfg->n_slots);
     for (Slot &sl : s->slots) {
@@ -439,6 +468,7 @@ ctp_status ctp_server_submit(ctp_server *srv, const ctp_plan *plan, ctp_directio
     ctp_plan_bytes(plan, out_dtype, 1, &vb_out, &sb_out);
     r->in_bytes = dir == CTP_FORWARD ? vb_in : sb_in;
     r->out_bytes = dir == CTP_FORWARD ? sb_out : vb_out;
+    r->work = ctp::plan_work(plan);
     size_t ws = 0;
     if (call_workspace(r.get(), 1, &ws) != CTP_OK)
         return CTP_EINVAL;
@@ -562,6 +592,39 @@ ctp_status ctp_server_release(ctp_server *srv, uint64_t ticket, hipStream_t cons
     if (--b->live == 0)
         srv->releasing.push_back(b);
     srv->wake.notify_one();
+    return CTP_OK;
+}
+
+ctp_status ctp_server_cancel(ctp_server *srv, uint64_t ticket)
+{
+    ctp::clear_error();
+    if (srv == nullptr)
+        return ctp::set_error(CTP_EINVAL, "NULL server");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->reqs.find(ticket);
+        if (it == srv->reqs.end())
+            return ctp::set_error(CTP_EINVAL, "unknown or released ticket");
+        Request *r = it->second.get();
+        if (r->state != Request::kQueued)
+            return ctp::set_error(CTP_EINVAL, r->state == Request::kRunning
+                                                  ? "request is running: it can no longer be cancelled"
+                                                  : "request has already finished");
+        for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
+            if (*q == r) {
+                srv->queue.erase(q);
+                break;
+            }
+        r->state = Request::kFailed;
+        r->err = CTP_ECANCELED;
+        r->msg = "request cancelled before it ran";
+        r->t_done = now_ns();
+        srv->event_pool.push_back(r->ready);
+        r->ready = nullptr;
+        ++srv->stats.cancelled;
+        srv->done_cv.notify_all();
+    }
+    srv->wake.notify_one();      // a head that was waiting for memory may have gone
     return CTP_OK;
 }
 

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctproj.so")
 
 CTP_OK, CTP_EINVAL, CTP_EUNSUPPORTED, CTP_ENOMEM, CTP_EDEVICE, CTP_ETIMEOUT = 0, -1, -2, -3, -4, -5
+CTP_ECANCELED = -6
 CTP_FAN2D, CTP_CONE_CIRC, CTP_CONE_NONCIRC = 0, 1, 2
 CTP_DET_FLAT, CTP_DET_CURVED = 0, 1
 CTP_SF, CTP_DD = 0, 1
@@ -41,8 +42,8 @@ EXPORTED = ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes", "ctp_worksp
             "ctp_last_error")
 # include/ctserve.h
 EXPORTED_SERVER = ("ctp_server_create", "ctp_server_submit", "ctp_server_wait",
-                   "ctp_server_query", "ctp_server_info", "ctp_server_release",
-                   "ctp_server_get_stats", "ctp_server_destroy")
+                   "ctp_server_query", "ctp_server_info", "ctp_server_cancel",
+                   "ctp_server_release", "ctp_server_get_stats", "ctp_server_destroy")
 
 
 class CtpError(RuntimeError):
@@ -64,7 +65,8 @@ class _Desc(ctypes.Structure):
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
-                ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+                ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("age_cap_us", ctypes.c_int64)]
 
 
 class _RequestInfo(ctypes.Structure):
@@ -75,7 +77,7 @@ class _RequestInfo(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("failed", ctypes.c_int64), ("calls", ctypes.c_int64),
-                ("max_running", ctypes.c_int32), ("max_batch_seen", ctypes.c_int32),
+                ("cancelled", ctypes.c_int64), ("max_running", ctypes.c_int32), ("max_batch_seen", ctypes.c_int32),
                 ("arena_peak", ctypes.c_size_t)]
 
 
@@ -117,6 +119,7 @@ def lib() -> ctypes.CDLL:
             L.ctp_server_query.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(vp)]
             L.ctp_server_info.argtypes = [vp, u64, ctypes.POINTER(_RequestInfo)]
+            L.ctp_server_cancel.argtypes = [vp, u64]
             L.ctp_server_release.argtypes = [vp, u64, vp]
             L.ctp_server_get_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
             L.ctp_server_destroy.argtypes = [vp]
@@ -253,6 +256,19 @@ def _workspace(plan: Plan, direction: int, batch: int, device, vol_dtype=CTP_F32
     return ws, need
 
 
+def _default_workspace(plan: Plan, direction: int, batch: int, device, vd, sd, stream):
+    """The cached workspace for a call on `stream`.  When the call runs on another stream than
+    the current one, the caching allocator is told (record_stream), so that the block is not
+    handed to a new allocation while that call may still use it; a raw stream handle gives the
+    allocator nothing to track, so it needs an explicit workspace."""
+    ws, nbytes = _workspace(plan, direction, batch, device, vd, sd)
+    if ws is not None and stream is not None:
+        if not hasattr(stream, "cuda_stream"):
+            raise ValueError("pass workspace= with a raw stream handle")
+        ws.record_stream(stream)
+    return ws, nbytes
+
+
 def _check_tensor(t, shape, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -275,7 +291,7 @@ def ctp_project(plan: Plan, vol, sino, accumulate: bool = False, workspace=None,
         raise ValueError("vol and sino batch sizes differ")
     vd, sd = _dtype_code(vol), _dtype_code(sino)
     if workspace is None:
-        ws, nbytes = _workspace(plan, CTP_FORWARD, batch, vol.device, vd, sd)
+        ws, nbytes = _default_workspace(plan, CTP_FORWARD, batch, vol.device, vd, sd, stream)
     else:
         ws, nbytes = workspace, workspace.numel() * workspace.element_size()
     _check(lib().ctp_project(plan.handle, vol.data_ptr(), vd, sino.data_ptr(), sd,
@@ -296,7 +312,7 @@ def ctp_backproject(plan: Plan, sino, vol, accumulate: bool = False, workspace=N
         raise ValueError("vol and sino batch sizes differ")
     vd, sd = _dtype_code(vol), _dtype_code(sino)
     if workspace is None:
-        ws, nbytes = _workspace(plan, CTP_BACKWARD, batch, vol.device, vd, sd)
+        ws, nbytes = _default_workspace(plan, CTP_BACKWARD, batch, vol.device, vd, sd, stream)
     else:
         ws, nbytes = workspace, workspace.numel() * workspace.element_size()
     _check(lib().ctp_backproject(plan.handle, sino.data_ptr(), sd, vol.data_ptr(), vd,
@@ -367,15 +383,19 @@ class Server:
     view into the arena (valid until ``release``).  The input tensor is kept referenced until its
     request has finished.  Outputs hold arena memory until released: a client that keeps every
     result can make later requests wait for memory that never frees (``wait`` then times out);
-    admission needs one contiguous block per call.
+    admission needs one contiguous block per call.  Requests that have waited ``age_cap_s`` are
+    served in arrival order; younger ones smallest first (``age_cap_s=0``: strict arrival
+    order).
     """
 
-    def __init__(self, arena_bytes: int, n_slots: int = 4, max_batch: int = 16, device=None):
+    def __init__(self, arena_bytes: int, n_slots: int = 4, max_batch: int = 16, device=None,
+                 age_cap_s: float = 0.05):
         import torch
         self.device = torch.device(device or "cuda")
         # uint8 arena; torch's allocations are at least 256-byte aligned
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
-        cfg = _ServerConfig(self.arena.data_ptr(), int(arena_bytes), int(n_slots), int(max_batch))
+        cfg = _ServerConfig(self.arena.data_ptr(), int(arena_bytes), int(n_slots), int(max_batch),
+                            int(round(age_cap_s * 1e6)))
         out = ctypes.c_void_p()
         _check(lib().ctp_server_create(ctypes.byref(cfg), ctypes.byref(out)), "ctp_server_create")
         self.handle = out
@@ -424,6 +444,13 @@ class Server:
         _check(lib().ctp_server_info(self.handle, ticket, ctypes.byref(i)), "ctp_server_info")
         return {"submit_ns": i.submit_ns, "admit_ns": i.admit_ns, "done_ns": i.done_ns,
                 "batch": i.batch, "slot": i.slot}
+
+    def cancel(self, ticket: int):
+        """Remove a request that has not started; its wait then raises CtpError with status
+        CTP_ECANCELED.  The ticket must still be released."""
+        _check(lib().ctp_server_cancel(self.handle, ticket), "ctp_server_cancel")
+        x, plan, out_code, shape = self._pending[ticket]
+        self._pending[ticket] = (None, plan, out_code, shape)
 
     def release(self, ticket: int, stream=None):
         """Return the request's output to the arena once the work queued so far on ``stream``

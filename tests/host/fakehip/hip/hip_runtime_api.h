@@ -7,7 +7,8 @@
 typedef enum {
     hipSuccess = 0,
     hipErrorInvalidValue = 1,
-    hipErrorNotReady = 600
+    hipErrorNotReady = 600,
+    hipErrorLaunchFailure = 719
 } hipError_t;
 
 struct SimStream;

@@ -106,18 +106,40 @@ static void batch_candidates_test()
     int p1, p2;
     auto key = [](const Q &q) { return ctp::BatchKey{q.plan, q.dir, q.in_dt, q.out_dt}; };
     std::deque<Q> q;
-    CHECK(ctp::batch_candidates(q, 4, key).empty());
+    CHECK(ctp::batch_candidates(q, 0, 4, key).empty());
     q = {{&p1, 0, 0, 0}, {&p2, 0, 0, 0}, {&p1, 0, 0, 0}, {&p1, 1, 0, 0}, {&p1, 0, 0, 1},
          {&p1, 0, 0, 0}, {&p1, 0, 0, 0}};
-    auto c = ctp::batch_candidates(q, 8, key);
+    auto c = ctp::batch_candidates(q, 0, 8, key);
     CHECK((c == std::vector<size_t>{0, 2, 5, 6}));       // same plan, direction and dtypes
-    c = ctp::batch_candidates(q, 2, key);
+    c = ctp::batch_candidates(q, 0, 2, key);
     CHECK((c == std::vector<size_t>{0, 2}));             // at most max_batch, oldest first
-    c = ctp::batch_candidates(q, 0, key);
+    c = ctp::batch_candidates(q, 0, 0, key);
     CHECK(c.empty());
-    q.pop_front();
-    c = ctp::batch_candidates(q, 8, key);
-    CHECK((c == std::vector<size_t>{0}));                // a lone head is served alone
+    c = ctp::batch_candidates(q, 5, 3, key);
+    CHECK((c == std::vector<size_t>{5, 0, 2}));          // head first, then arrival order
+    c = ctp::batch_candidates(q, 1, 8, key);
+    CHECK((c == std::vector<size_t>{1}));                // a lone head is served alone
+    CHECK(ctp::batch_candidates(q, 7, 8, key).empty());  // past the end
+}
+
+struct W { double work; int64_t t; };
+
+static void head_order_test()
+{
+    auto info = [](const W &w) { return std::make_pair(w.work, w.t); };
+    std::deque<W> q = {{5.0, 0}, {1.0, 10}, {3.0, 20}, {1.0, 30}, {9.0, 40}};
+    size_t n_aged = 99;
+    // no cap: arrival order, everything counts as aged
+    auto o = ctp::head_order(q, 100, 0, info, &n_aged);
+    CHECK((o == std::vector<size_t>{0, 1, 2, 3, 4}) && n_aged == 5);
+    // cap 1000 at time 100: nothing aged, cheapest first, ties in arrival order
+    o = ctp::head_order(q, 100, 1000, info, &n_aged);
+    CHECK((o == std::vector<size_t>{1, 3, 2, 0, 4}) && n_aged == 0);
+    // cap 85 at time 100: requests submitted at 0 and 10 are aged and lead, oldest first
+    o = ctp::head_order(q, 100, 85, info, &n_aged);
+    CHECK((o == std::vector<size_t>{0, 1, 3, 2, 4}) && n_aged == 2);
+    std::deque<W> e;
+    CHECK(ctp::head_order(e, 0, 10, info, &n_aged).empty() && n_aged == 0);
 }
 
 int main()
@@ -134,6 +156,7 @@ int main()
     CHECK(a.alloc_high(300) == 4096 - 512 && a.alloc(1) == 0 && a.alloc_high(256) == 4096 - 768);
     CHECK(a.alloc_high(SIZE_MAX - 10) == Arena::kFail);
     batch_candidates_test();
+    head_order_test();
     std::printf("ok\n");
     return 0;
 }

@@ -5,6 +5,10 @@
 // Scenarios: bursts of mixed requests (large calls first, then many small ones of several
 // plans, directions and storage types) with outputs held until every request is done, as a
 // client that reads its results in submission order would; every request must complete.
+// Failure handling: calls that fail to launch and calls whose completion reports a device error
+// (injected through plans marked to fail) fail their own requests only, while every other
+// request in flight completes and all arena memory comes back; queued requests can be
+// cancelled; small requests overtake a long queue of large ones until the age cap.
 // Prints "ok" and exits 0 on success.
 #include "../../paper_2503_16741_amd/csrc/server.cpp"
 
@@ -18,9 +22,11 @@
 struct SimStream {
     std::mutex mu;
     double busy_until = 0.0;     // microseconds on the steady clock
+    bool poisoned = false;       // the work enqueued since the last event record failed
 };
 struct SimEvent {
     std::atomic<double> ready_at{0.0};
+    std::atomic<bool> failed{false};
 };
 
 static double now_us()
@@ -57,13 +63,29 @@ hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned)
 }
 hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { *e = new SimEvent(); return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
-hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) { e->ready_at = enqueue(s, 0.0); return hipSuccess; }
-hipError_t hipEventQuery(hipEvent_t e) { return now_us() >= e->ready_at ? hipSuccess : hipErrorNotReady; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s)
+{
+    e->ready_at = enqueue(s, 0.0);
+    bool bad = false;
+    if (s != nullptr) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        bad = s->poisoned;
+        s->poisoned = false;
+    }
+    e->failed = bad;
+    return hipSuccess;
+}
+hipError_t hipEventQuery(hipEvent_t e)
+{
+    if (now_us() < e->ready_at)
+        return hipErrorNotReady;
+    return e->failed ? hipErrorLaunchFailure : hipSuccess;
+}
 hipError_t hipEventSynchronize(hipEvent_t e)
 {
-    while (hipEventQuery(e) != hipSuccess)
+    while (hipEventQuery(e) == hipErrorNotReady)
         std::this_thread::yield();
-    return hipSuccess;
+    return hipEventQuery(e);
 }
 hipError_t hipMemcpyAsync(void *, const void *, size_t n, hipMemcpyKind, hipStream_t s)
 {
@@ -79,6 +101,7 @@ struct ctp_plan {
     bool two_d = false, recon = false, sf = true;
     size_t nvox = 0, ncell = 0, plane = 0;
     double us_per_item = 10.0;
+    int fail = 0;                // 1: the call fails to launch; 2: it fails on the device
 };
 
 static size_t a256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -89,6 +112,7 @@ namespace ctp {
 ctp_status set_error(ctp_status st, const std::string &msg) { sim_err = msg; return st; }
 void clear_error() { sim_err.clear(); }
 int plan_device(const ctp_plan *plan) { return plan->device; }
+double plan_work(const ctp_plan *plan) { return plan->us_per_item; }
 }  // namespace ctp
 extern "C" const char *ctp_last_error(void) { return sim_err.c_str(); }
 
@@ -132,7 +156,13 @@ static ctp_status sim_call(const ctp_plan *p, ctp_direction dir, ctp_dtype vd, c
         ++bad_calls;
         return ctp::set_error(CTP_EINVAL, "workspace too small or misaligned");
     }
+    if (p->fail == 1)
+        return ctp::set_error(CTP_EDEVICE, "injected launch failure");
     enqueue(st, p->us_per_item * (double)batch);
+    if (p->fail == 2) {
+        std::lock_guard<std::mutex> lk(st->mu);
+        st->poisoned = true;
+    }
     return CTP_OK;
 }
 
@@ -186,7 +216,8 @@ static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, i
         r.out = rng() % 10 < 7 ? r.in : CTP_F32;
         reqs.push_back(r);
     }
-    ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch};
+    ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch,
+                          seed % 2 ? 0 : 20000};
     ctp_server *srv = nullptr;
     CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
     static char dummy_input[16];
@@ -223,6 +254,156 @@ static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, i
     CHECK(ctp_server_destroy(srv) == CTP_OK);
 }
 
+static ctp_server *make_server(size_t arena_bytes, int slots, int max_batch, int64_t age_cap_us)
+{
+    ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch,
+                          age_cap_us};
+    ctp_server *srv = nullptr;
+    CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
+    return srv;
+}
+
+// Release every ticket and wait (bounded) until the arena is empty again.
+static void release_all_and_drain(ctp_server *srv, const std::vector<uint64_t> &tickets)
+{
+    for (uint64_t t : tickets)
+        CHECK(ctp_server_release(srv, t, nullptr) == CTP_OK);
+    for (int i = 0; i < 20000; ++i) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (srv->alloc.in_use() == 0 && srv->releasing.empty())
+                return;
+        }
+        srv->wake.notify_one();
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    CHECK(!"arena memory did not come back");
+}
+
+// A mix in which some calls fail to launch and some fail on the device: exactly the requests of
+// the failing plans fail, with the device status, and everything else completes.
+static void failure_injection(unsigned seed)
+{
+    ctp_plan ok_a, ok_b, bad_launch, bad_device;
+    ok_a.nvox = 20 * 20 * 20; ok_a.ncell = 16 * 30 * 30; ok_a.us_per_item = 80;
+    ok_b.two_d = true; ok_b.nvox = ok_b.plane = 30 * 30; ok_b.ncell = 20 * 64; ok_b.us_per_item = 30;
+    bad_launch = ok_a; bad_launch.fail = 1;
+    bad_device = ok_b; bad_device.fail = 2;
+    ctp_plan *plans[4] = {&ok_a, &ok_b, &bad_launch, &bad_device};
+    std::mt19937 rng(seed);
+    ctp_server *srv = make_server(64u << 20, 3, 4, seed % 2 ? 0 : 5000);
+    static char dummy_input[16];
+    std::vector<uint64_t> tickets;
+    std::vector<int> which;
+    for (int i = 0; i < 120; ++i) {
+        const int k = (int)(rng() % 4);
+        uint64_t t = 0;
+        CHECK(ctp_server_submit(srv, plans[k], rng() % 2 ? CTP_FORWARD : CTP_BACKWARD, dummy_input,
+                                CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+        tickets.push_back(t);
+        which.push_back(k);
+    }
+    int n_fail = 0;
+    for (size_t i = 0; i < tickets.size(); ++i) {
+        void *res = nullptr;
+        const ctp_status st = ctp_server_wait(srv, tickets[i], 20 * 1000 * 1000, &res);
+        if (which[i] >= 2) {
+            CHECK(st == CTP_EDEVICE);
+            ++n_fail;
+        } else {
+            CHECK(st == CTP_OK && res != nullptr);
+        }
+    }
+    ctp_server_stats s{};
+    ctp_server_get_stats(srv, &s);
+    CHECK(s.failed == n_fail && s.completed == (int64_t)tickets.size() - n_fail);
+    release_all_and_drain(srv, tickets);
+    CHECK(ctp_server_destroy(srv) == CTP_OK);
+}
+
+// Cancelling queued requests on a one-slot server held busy by a long call.
+static void cancellation()
+{
+    ctp_plan slow, quick;
+    slow.nvox = 32 * 32 * 32; slow.ncell = 20 * 40 * 40; slow.us_per_item = 50000;
+    quick.nvox = 8 * 8 * 8; quick.ncell = 4 * 10 * 10; quick.us_per_item = 100;
+    ctp_server *srv = make_server(64u << 20, 1, 1, 0);
+    static char dummy_input[16];
+    uint64_t busy = 0;
+    CHECK(ctp_server_submit(srv, &slow, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &busy) == CTP_OK);
+    std::vector<uint64_t> tickets;
+    for (int i = 0; i < 10; ++i) {
+        uint64_t t = 0;
+        CHECK(ctp_server_submit(srv, &quick, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+        tickets.push_back(t);
+    }
+    std::this_thread::sleep_for(std::chrono::milliseconds(5));   // the slow call is running
+    CHECK(ctp_server_cancel(srv, busy) == CTP_EINVAL);             // running: not cancellable
+    for (size_t i = 0; i < tickets.size(); i += 2)
+        CHECK(ctp_server_cancel(srv, tickets[i]) == CTP_OK);
+    CHECK(ctp_server_cancel(srv, tickets[0]) == CTP_EINVAL);       // already cancelled
+    CHECK(ctp_server_cancel(srv, 987654321) == CTP_EINVAL);        // unknown ticket
+    CHECK(ctp_server_wait(srv, busy, -1, nullptr) == CTP_OK);
+    for (size_t i = 0; i < tickets.size(); ++i) {
+        const ctp_status st = ctp_server_wait(srv, tickets[i], 20 * 1000 * 1000, nullptr);
+        CHECK(st == (i % 2 == 0 ? CTP_ECANCELED : CTP_OK));
+    }
+    ctp_server_stats s{};
+    ctp_server_get_stats(srv, &s);
+    CHECK(s.cancelled == 5 && s.completed == 6 && s.calls == 6);
+    tickets.push_back(busy);
+    release_all_and_drain(srv, tickets);
+    CHECK(ctp_server_destroy(srv) == CTP_OK);
+}
+
+// Order: behind a queue of long calls, short requests start first (smallest work first); once
+// requests have waited past the age cap they run in arrival order.
+static void ordering()
+{
+    ctp_plan big, small;
+    big.nvox = 32 * 32 * 32; big.ncell = 20 * 40 * 40; big.us_per_item = 20000;
+    small.nvox = 8 * 8 * 8; small.ncell = 4 * 10 * 10; small.us_per_item = 200;
+    static char dummy_input[16];
+    for (int64_t cap_us : {(int64_t)0, (int64_t)1000000, (int64_t)10000}) {
+        ctp_server *srv = make_server(256u << 20, 1, 1, cap_us);
+        std::vector<uint64_t> bigs, smalls;
+        for (int i = 0; i < 4; ++i) {
+            uint64_t t = 0;
+            CHECK(ctp_server_submit(srv, &big, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+            bigs.push_back(t);
+            if (i == 0)   // the first big call is running before anything else is queued
+                std::this_thread::sleep_for(std::chrono::milliseconds(3));
+        }
+        for (int i = 0; i < 4; ++i) {
+            uint64_t t = 0;
+            CHECK(ctp_server_submit(srv, &small, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+            smalls.push_back(t);
+        }
+        for (uint64_t t : bigs)
+            CHECK(ctp_server_wait(srv, t, 20 * 1000 * 1000, nullptr) == CTP_OK);
+        for (uint64_t t : smalls)
+            CHECK(ctp_server_wait(srv, t, 20 * 1000 * 1000, nullptr) == CTP_OK);
+        ctp_request_info b1{}, s_last{};
+        CHECK(ctp_server_info(srv, bigs[1], &b1) == CTP_OK);
+        CHECK(ctp_server_info(srv, smalls[3], &s_last) == CTP_OK);
+        if (cap_us == 0)
+            CHECK(s_last.admit_ns > b1.admit_ns);      // arrival order: the smalls wait
+        else if (cap_us == 1000000)
+            CHECK(s_last.admit_ns < b1.admit_ns);      // smallest first: they overtake
+        else {
+            // cap 10 ms: when the first big call ends (20 ms) every queued request has waited
+            // ~17 ms, past the cap, so they run in arrival order: the smalls after the last big
+            ctp_request_info b3{};
+            CHECK(ctp_server_info(srv, bigs[3], &b3) == CTP_OK);
+            CHECK(s_last.admit_ns > b3.admit_ns);
+        }
+        std::vector<uint64_t> all(bigs);
+        all.insert(all.end(), smalls.begin(), smalls.end());
+        release_all_and_drain(srv, all);
+        CHECK(ctp_server_destroy(srv) == CTP_OK);
+    }
+}
+
 int main()
 {
     // the configuration of the GPU serving test, then tighter arenas and other slot counts
@@ -234,6 +415,10 @@ int main()
         burst(300 + seed, 64u << 20, 3, 4, 0, 200);
     }
     CHECK(bad_calls == 0);
+    for (unsigned seed = 1; seed <= 4; ++seed)
+        failure_injection(seed);
+    cancellation();
+    ordering();
     std::printf("ok\n");
     return 0;
 }

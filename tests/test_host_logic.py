@@ -34,7 +34,10 @@ def test_serving_engine_simulated_device(tmp_path):
     events, stub projector calls with the library's workspace formulas): bursts of mixed
     requests whose outputs the client holds until all are done must all complete, with every
     call given a large enough workspace.  A scratch block placed between outputs used to leave
-    a request that could never be admitted (fragmentation); scratch now comes from the top."""
+    a request that could never be admitted (fragmentation); scratch now comes from the top.
+    Failure injection: calls that fail to launch or fail on the device fail only their own
+    requests, the others complete and the arena empties; queued requests can be cancelled;
+    short requests overtake long ones until the age cap, then arrival order holds."""
     exe = _cc(tmp_path, os.path.join(ROOT, "tests", "host", "serve_sim.cpp"), "sim",
               ["g++", "-std=c++17", "-O1", "-pthread", "-fsanitize=address,undefined",
                "-fno-sanitize-recover=all", "-I" + os.path.join(ROOT, "tests", "host", "fakehip")])
@@ -53,10 +56,11 @@ int main(void) {
     P(ctp_geometry_desc, du); P(ctp_geometry_desc, n_views); P(ctp_geometry_desc, theta);
     P(ctp_geometry_desc, v_ofst); P(ctp_geometry_desc, len_theta); P(ctp_geometry_desc, len_v_ofst);
     S(ctp_server_config); P(ctp_server_config, arena_bytes); P(ctp_server_config, n_slots);
-    P(ctp_server_config, max_batch);
+    P(ctp_server_config, max_batch); P(ctp_server_config, age_cap_us);
     S(ctp_request_info); P(ctp_request_info, done_ns); P(ctp_request_info, batch);
     P(ctp_request_info, slot);
-    S(ctp_server_stats); P(ctp_server_stats, calls); P(ctp_server_stats, max_running);
+    S(ctp_server_stats); P(ctp_server_stats, calls); P(ctp_server_stats, cancelled);
+    P(ctp_server_stats, max_running);
     P(ctp_server_stats, max_batch_seen); P(ctp_server_stats, arena_peak);
     return 0;
 }
