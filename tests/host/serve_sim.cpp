@@ -321,6 +321,21 @@ static void failure_injection(unsigned seed)
     CHECK(ctp_server_destroy(srv) == CTP_OK);
 }
 
+// Wait (bounded) until the request's call has been admitted: the server thread may start late
+// on a loaded host, so a fixed sleep is not enough.
+static void wait_running(ctp_server *srv, uint64_t ticket)
+{
+    for (int i = 0; i < 20000; ++i) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (srv->reqs.at(ticket)->state != Request::kQueued)
+                return;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    CHECK(!"request was never admitted");
+}
+
 // Cancelling queued requests on a one-slot server held busy by a long call.
 static void cancellation()
 {
@@ -337,7 +352,7 @@ static void cancellation()
         CHECK(ctp_server_submit(srv, &quick, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
         tickets.push_back(t);
     }
-    std::this_thread::sleep_for(std::chrono::milliseconds(5));   // the slow call is running
+    wait_running(srv, busy);
     CHECK(ctp_server_cancel(srv, busy) == CTP_EINVAL);             // running: not cancellable
     for (size_t i = 0; i < tickets.size(); i += 2)
         CHECK(ctp_server_cancel(srv, tickets[i]) == CTP_OK);
@@ -372,7 +387,7 @@ static void ordering()
             CHECK(ctp_server_submit(srv, &big, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
             bigs.push_back(t);
             if (i == 0)   // the first big call is running before anything else is queued
-                std::this_thread::sleep_for(std::chrono::milliseconds(3));
+                wait_running(srv, t);
         }
         for (int i = 0; i < 4; ++i) {
             uint64_t t = 0;
