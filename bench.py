@@ -201,20 +201,27 @@ def cpu_full():
             print(f"[cpu-full] {r}", file=sys.stderr, flush=True)
             runs.append(r)
     res = dict(hi, runs=runs)
+    print(json.dumps(res), flush=True)
+    write_cpu_full(res)
+
+
+def write_cpu_full(res):
+    """profiles/cpu_oracle_full.json and .md from the result of cpu_full() (the JSON line that
+    `--cpu-full` prints, which `--cpu-full-summarize FILE` reads back)."""
     with open(os.path.join(ROOT, "profiles", "cpu_oracle_full.json"), "w") as fh:
         json.dump(res, fh, indent=1)
     lines = ["# FP64 CPU oracle on whole scans", "", "Command (repository root, GPU box host):", "",
-             "```", "python3 bench.py --cpu-full", "```", "",
-             f"Host: {hi['cpu_model']}; {hi['nproc']} logical CPUs, {hi['affinity']} in this "
-             f"process's affinity mask; the oracle ran {hi['oracle_threads']} OpenMP threads "
+             "```", "python3 bench.py --cpu-full > cpu_full.json",
+             "python3 bench.py --cpu-full-summarize cpu_full.json", "```", "",
+             f"Host: {res['cpu_model']}; {res['nproc']} logical CPUs, {res['affinity']} in this "
+             f"process's affinity mask; the oracle ran {res['oracle_threads']} OpenMP threads "
              "(forward parallel over views, adjoint over voxels).", "",
              "| scan | method | forward s | adjoint s | GUPS (pair) |", "|---|---|---|---|---|"]
-    for r in runs:
+    for r in res["runs"]:
         lines.append(f"| {r['scan']} | {r['method'].upper()} | {r['forward_s']} | "
                      f"{r['adjoint_s']} | {r['gups_pair']} |")
     with open(os.path.join(ROOT, "profiles", "cpu_oracle_full.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print(json.dumps(res), flush=True)
 
 
 def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, seed=0,
@@ -386,6 +393,8 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the FP64 oracle over whole scans (minutes) and write its summary")
+    ap.add_argument("--cpu-full-summarize", metavar="JSON",
+                    help="write profiles/cpu_oracle_full.* from a saved --cpu-full output line")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB device copy, one SF forward and one SF back projection "
                          "(for FETCH_SIZE / WRITE_SIZE counter runs) and exit")
@@ -408,6 +417,10 @@ def main():
         return
     if args.cpu_full:
         cpu_full()
+        return
+    if args.cpu_full_summarize:
+        with open(args.cpu_full_summarize) as fh:
+            write_cpu_full(json.loads(fh.read().strip().splitlines()[-1]))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -476,6 +489,10 @@ def main():
         torch.cuda.synchronize()
         ctproj.ctp_project(plan, vol, sino)
         ctproj.ctp_backproject(plan, sino, back)
+        if scan != "noncirc_c4" and method == "sf":
+            # the ramp filter of the same scan (FDK weighting) in place
+            plan_r = ctproj.ctp_plan_create(gp, "sf", "recon")
+            ctproj.ctp_ramp_filter(plan_r, sino, sino)
         torch.cuda.synchronize()
         print(json.dumps({"probe": name, "copy_bytes": src.numel() * 4}), flush=True)
         return
