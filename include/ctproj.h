@@ -152,6 +152,22 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
                        void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * ctp_project without a workspace argument and without any device allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is a static array of the library,
+ * 96 MiB (100663296 bytes) per device, which each device that loads the library holds until
+ * the process ends.  Same arguments, layouts, results and errors as ctp_project, plus
+ * CTP_EINVAL when the call's forward workspace (ctp_workspace_bytes) exceeds 96 MiB (e.g. one
+ * 256^3 FP32 volume fits, two do not) and CTP_EDEVICE when the array's address cannot be
+ * obtained.  Every call on a device uses that device's one array: calls that overlap on one
+ * device (other streams or host threads) race and must be serialised by the caller.  Nothing
+ * in the array needs to start at zero; its contents after a call are scratch.
+ */
+ctp_status ctp_project_static(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype,
+                              void *sino, ctp_dtype sino_dtype, int64_t batch, int accumulate,
+                              hipStream_t stream);
+
+/*
  * Back projection (Eq. 2), the exact transpose of ctp_project with the same weights:
  * vol = A^T sino, or vol += A^T sino when accumulate != 0.  Arguments as for ctp_project,
  * with the workspace sized by ctp_workspace_bytes(plan, CTP_BACKWARD, vol_dtype, sino_dtype,

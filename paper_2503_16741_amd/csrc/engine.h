@@ -113,6 +113,10 @@ hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *vi
 hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,
                            const float *ysc, float *vol, int64_t batch, int accumulate,
                            hipStream_t st);
+// Device address of this device's copy of the library's static scratch array (looked up once
+// per device, then cached), kStaticScratchBytes long: the workspace of ctp_project_static.
+constexpr size_t kStaticScratchBytes = (size_t)96 << 20;
+hipError_t static_scratch(void **ptr);
 // Cosine-weighted ramp filter of every detector row (circular scans).  window: 0 = Ram-Lak,
 // 1 = Shepp-Logan; dbeta: angular step of the scan; in / out storage types as above (in and
 // out may be the same buffer when their types agree).

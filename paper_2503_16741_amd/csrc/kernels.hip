@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #ifndef CTP_FWD_FAST
 #define CTP_FWD_FAST 1
@@ -2101,6 +2103,39 @@ hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *v
                            hipStream_t st)
 {
     return dispatch<BwdOp>(c, p, c, views, ysc, vol, batch, accumulate, st);
+}
+
+// ---- library-owned scratch of the allocation-free forward entry point ----------------------
+//
+// One array per device (each device that loads this code object holds its own copy until the
+// process ends).  In host code `scratch` only names the symbol: its device address is looked up
+// once per device with hipGetSymbolAddress and cached; kernels receive that address.  Calls
+// that use it share it, so overlapping calls on one device race.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;   // device -> device address of its copy of `scratch`
+}  // namespace
+
+hipError_t static_scratch(void **ptr)
+{
+    *ptr = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return hipSuccess;
 }
 
 }  // namespace ctp

@@ -587,6 +587,34 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
                         stream);
 }
 
+ctp_status ctp_project_static(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype,
+                              void *sino, ctp_dtype sino_dtype, int64_t batch, int accumulate,
+                              hipStream_t stream)
+{
+    g_last_error.clear();
+    // the same checks as ctp_project, then the size of the call's workspace against the array
+    size_t need = 0;
+    ctp_status st = ctp_workspace_bytes(plan, CTP_FORWARD, vol_dtype, sino_dtype, batch, &need);
+    if (st != CTP_OK)
+        return st;
+    if (need > ctp::kStaticScratchBytes)
+        return fail(CTP_EINVAL, "call needs " + std::to_string(need) +
+                                    " bytes of scratch; the static scratch holds " +
+                                    std::to_string(ctp::kStaticScratchBytes) +
+                                    " (use ctp_project with a workspace)");
+    void *scratch = nullptr;
+    const hipError_t e = ctp::static_scratch(&scratch);
+    if (e != hipSuccess)
+        return fail(CTP_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
+    ctp::Params p;
+    st = prepare_call(plan, vol, sino, vol_dtype, sino_dtype, batch, scratch,
+                      ctp::kStaticScratchBytes, CTP_FORWARD, p);
+    if (st != CTP_OK)
+        return st;
+    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, accumulate, scratch, p,
+                        stream);
+}
+
 ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *vol,
                            ctp_dtype vol_dtype, int64_t batch, int accumulate, void *workspace,
                            size_t workspace_bytes, hipStream_t stream)

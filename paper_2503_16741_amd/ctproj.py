@@ -38,8 +38,8 @@ MODE = {"proj": CTP_MODE_PROJ, "recon": CTP_MODE_RECON}
 WINDOW = {"ram-lak": CTP_WINDOW_RAMLAK, "shepp-logan": CTP_WINDOW_SHEPP_LOGAN}
 
 EXPORTED = ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes", "ctp_workspace_bytes",
-            "ctp_project", "ctp_backproject", "ctp_ramp_filter", "ctp_status_string",
-            "ctp_last_error")
+            "ctp_project", "ctp_project_static", "ctp_backproject", "ctp_ramp_filter",
+            "ctp_status_string", "ctp_last_error")
 # include/ctserve.h
 EXPORTED_SERVER = ("ctp_server_create", "ctp_server_submit", "ctp_server_wait",
                    "ctp_server_query", "ctp_server_info", "ctp_server_cancel",
@@ -108,8 +108,11 @@ def lib() -> ctypes.CDLL:
                                       vp, sz, vp]
             L.ctp_backproject.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i64, ctypes.c_int,
                                           vp, sz, vp]
+            L.ctp_project_static.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i64,
+                                             ctypes.c_int, vp]
             for f in ("ctp_plan_create", "ctp_plan_destroy", "ctp_plan_bytes",
-                      "ctp_workspace_bytes", "ctp_project", "ctp_backproject", "ctp_ramp_filter"):
+                      "ctp_workspace_bytes", "ctp_project", "ctp_project_static",
+                      "ctp_backproject", "ctp_ramp_filter"):
                 getattr(L, f).restype = ctypes.c_int
             u64 = ctypes.c_uint64
             L.ctp_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
@@ -298,6 +301,21 @@ def ctp_project(plan: Plan, vol, sino, accumulate: bool = False, workspace=None,
                              batch, int(bool(accumulate)),
                              ws.data_ptr() if ws is not None else None, nbytes,
                              _stream_handle(stream)), "ctp_project")
+    return sino
+
+
+def ctp_project_static(plan: Plan, vol, sino, accumulate: bool = False, stream=None):
+    """sino (+)= A vol using the library's static per-device scratch (no allocation; calls on
+    one device must not overlap)."""
+    g = plan.geom
+    _check_tensor(vol, g.vol_shape, "vol")
+    _check_tensor(sino, g.sino_shape, "sino")
+    batch = vol.numel() // int(np.prod(g.vol_shape))
+    if sino.numel() != batch * int(np.prod(g.sino_shape)):
+        raise ValueError("vol and sino batch sizes differ")
+    _check(lib().ctp_project_static(plan.handle, vol.data_ptr(), _dtype_code(vol), sino.data_ptr(),
+                                    _dtype_code(sino), batch, int(bool(accumulate)),
+                                    _stream_handle(stream)), "ctp_project_static")
     return sino
 
 
