@@ -38,6 +38,7 @@ constexpr int kRowsMax = 512;    // detector rows (or 2D batch items) held in LD
 #endif
 constexpr int kZChunk = CTP_ZCHUNK; // voxels per lane along z in the back projector
 constexpr int kTile = 8;         // 8 x 8 voxel columns per wavefront tile
+constexpr int kNCRunMax = 16;    // longest non-circular column run (slices) of either direction
 
 // Per-view constants, object-centred coordinates (the object offset is folded into the
 // source and detector), FP32.  Built in FP64 on the host.  128 bytes.
@@ -81,6 +82,7 @@ struct Params {
     int64_t sino_view_stride;
     int64_t sino_b_stride;   // elements between batch items (3D)
     float eps;               // ramps narrower than this (cells) are steps
+    int nc_runs;             // non-circular SF: column runs allowed (see the plan's bound)
 };
 
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.

@@ -444,6 +444,346 @@ __device__ __forceinline__ float sf_amp(const ViewRec &V, const Params &P, float
     return g * fminf(fdiv(P.dx, fabsf(gx)), fdiv(P.dy, fabsf(gy)));
 }
 
+// ---- non-circular SF (flat detector): voxel-column runs -----------------------------------
+//
+// A tilted pose gives the detector axes z components, so along a voxel column the transaxial
+// corners (taken at each voxel's mid-plane) drift in u and the corners of one face lie at
+// different depths.  Along a column every corner's projection is a ratio of affine functions
+// of the slice (or face) index j, f(j) = (N0 + a j) / (D0 + b j) = f0 + s j / (1 + r j) with
+// s = (a - f0 b) / D0 and r = b / D0.  Within a run of slices it is evaluated as the
+// second-order expansion f0 + s j + c j^2, c = -s r, whose remainder |s| r^2 j^3 the plan
+// bounds (below 2e-5 cells or rows, else this path is off and every voxel is evaluated on its
+// own).  The difference of two corners' projections has a numerator affine in j, so two
+// corners change order at most once along a column: when the sorted order of the transaxial
+// corners, and the two corners that bound the faces' v-intervals, agree at both ends of the
+// column, they hold for all of it (otherwise the column takes the per-voxel path).
+
+// Slopes per slice of a view's projection numerators and depths.
+struct NCView {
+    float aU;   // Du dz eu_z: numerator of u (columns x mm)
+    float aV;   // Dv dz ev_z: numerator of v (rows x mm)
+    float bW;   // -dz n_z:    depth (mm)
+};
+
+__device__ __forceinline__ NCView nc_view(const ViewRec &V, const Params &P)
+{
+    NCView w;
+    w.aU = V.Du * P.dz * V.eu[2];
+    w.aV = V.Dv * P.dz * V.ev[2];
+    w.bW = -P.dz * V.n[2];
+    return w;
+}
+
+// f0, s, c of f(j) = (N0 + a j) / (D0 + b j) about j = 0 (see above).
+__device__ __forceinline__ void nc_expand(float N0, float D0, float a, float b, float &f0,
+                                          float &s, float &c)
+{
+    const float iD = fast_rcp(D0);
+    f0 = N0 * iD;
+    s = fmaf(-f0, b, a) * iD;
+    c = -s * (b * iD);
+}
+
+// A voxel column in one view.  NU, DU: numerators Du (a_c + da_k) and depths W_c + dW_k of the
+// four transaxial corners at the centre of slice 0, sorted by u; NV: numerators Dv (h + dh_k) of
+// the same corners at face 0 (the bottom of slice 0), whose depths are DU - bW / 2.  A face's
+// v-interval is the minimum and maximum of its four corners (which corners those are changes
+// along the column: near and far swap at the detector's central plane).  ok: the transaxial
+// order holds along the column, every depth is positive and the faces are increasing and
+// disjoint (voxel z's axial trapezoid rises over face z and falls over face z + 1); inside:
+// every face lies within rows [0, R - 1) of the row window.
+struct NCCol {
+    float NU[4], DU[4], NV[4];
+    bool ok, inside;
+};
+
+// v-interval [p, q] (rows, without cv) of face f of a column (corners NV, DU as in NCCol).
+__device__ __forceinline__ void nc_face(const float (&NV)[4], const float (&DU)[4],
+                                        const NCView &w, float f, float &p, float &q)
+{
+    p = 3.0e38f;
+    q = -3.0e38f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float v = fdiv(fmaf(f, w.aV, NV[k]), fmaf(f, w.bW, fmaf(-0.5f, w.bW, DU[k])));
+        p = fminf(p, v);
+        q = fmaxf(q, v);
+    }
+}
+
+// nf: the faces the runs walk (the slices rounded up to whole runs); cvr: V.cv minus the row
+// window's first row; R: rows in the window.
+__device__ __forceinline__ void nc_column(const ViewRec &V, const Params &P, const NCView &w,
+                                          float xc, float yc, float cvr, int R, int nf,
+                                          NCCol &c)
+{
+    const float hx = 0.5f * P.dx, hy = 0.5f * P.dy;
+    const float A0 = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], fmaf(P.z0, V.eu[2], -V.seu)));
+    const float W0 = V.sn - fmaf(xc, V.n[0], fmaf(yc, V.n[1], P.z0 * V.n[2]));
+    const float Hf = fmaf(xc, V.ev[0], fmaf(yc, V.ev[1], fmaf(P.z0 - 0.5f * P.dz, V.ev[2], -V.sev)));
+    const float zl = (float)(P.nz - 1), fl = (float)nf;
+    float k0[4], k1[4];
+    float dmin = 3.0e38f;      // smallest corner depth over the faces walked (affine in z)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float sx = (k & 1) ? hx : -hx, sy = (k & 2) ? hy : -hy;
+        const float dW = fmaf(sx, V.n[0], sy * V.n[1]);
+        c.NU[k] = V.Du * fmaf(sx, V.eu[0], fmaf(sy, V.eu[1], A0));
+        c.DU[k] = W0 - dW;
+        c.NV[k] = V.Dv * fmaf(sx, V.ev[0], fmaf(sy, V.ev[1], Hf));
+        const float df = fmaf(-0.5f, w.bW, c.DU[k]);
+        dmin = fminf(dmin, fminf(df, fmaf(fl, w.bW, df)));
+        k0[k] = fdiv(c.NU[k], c.DU[k]);
+        k1[k] = fdiv(fmaf(zl, w.aU, c.NU[k]), fmaf(zl, w.bW, c.DU[k]));
+    }
+    // transaxial corners sorted by u at slice 0, carrying their u at the last slice
+    auto ce = [&](int i, int j) {
+        const bool sw = k0[j] < k0[i];
+        const float a0 = k0[i], a1 = k1[i], a2 = c.NU[i], a3 = c.DU[i], a4 = c.NV[i];
+        k0[i] = sw ? k0[j] : a0; k0[j] = sw ? a0 : k0[j];
+        k1[i] = sw ? k1[j] : a1; k1[j] = sw ? a1 : k1[j];
+        c.NU[i] = sw ? c.NU[j] : a2; c.NU[j] = sw ? a2 : c.NU[j];
+        c.DU[i] = sw ? c.DU[j] : a3; c.DU[j] = sw ? a3 : c.DU[j];
+        c.NV[i] = sw ? c.NV[j] : a4; c.NV[j] = sw ? a4 : c.NV[j];
+    };
+    ce(0, 1); ce(2, 3); ce(0, 2); ce(1, 3); ce(1, 2);
+    const bool tstable = k1[0] <= k1[1] && k1[1] <= k1[2] && k1[2] <= k1[3];
+    // faces increasing and disjoint: p(f + 1) - q(f) at both ends (rows)
+    float p0, q0, p1, q1, pl, ql, pn, qn;
+    nc_face(c.NV, c.DU, w, 0.0f, p0, q0);
+    nc_face(c.NV, c.DU, w, 1.0f, p1, q1);
+    nc_face(c.NV, c.DU, w, fl - 1.0f, pl, ql);
+    nc_face(c.NV, c.DU, w, fl, pn, qn);
+    const float m = 1e-4f;
+    c.ok = dmin > 0.0f && tstable && p1 - q0 >= m && pn - ql >= m;
+    c.inside = p0 + cvr >= 0.0f && qn + cvr < (float)(R - 1);
+}
+
+// Slot weights of one voxel of a run: its transaxial corners t_k (columns relative to the run's
+// first cell, sorted; T0_k + j (s_k + j c_k) for the run's j-th voxel), the unit-height
+// trapezoid's cell
+// averages F1 over the K cells from floor(t0) (its width is below K - 1 cells), times val, in
+// the slots 0 .. K of the run's cells (floor(t0) is 0 or 1: the run's corners drift by less
+// than a cell).
+template <int K>
+__device__ __forceinline__ void nc_slot_weights(const float (&t)[4], float val, float eps,
+                                                float (&wv)[K + 1])
+{
+    float r1 = t[1] - t[0], r2 = t[3] - t[2];
+    const float rp = fmaxf(t[2] - t[1], 0.0f);
+    const bool s1 = r1 > eps, s2 = r2 > eps;
+    const float h1 = s1 ? 0.5f * fast_rcp(r1) : 0.0f, h2 = s2 ? 0.5f * fast_rcp(r2) : 0.0f;
+    r1 = s1 ? r1 : 0.0f;
+    r2 = s2 ? r2 : 0.0f;
+    const float area = fmaf(0.5f, r1 + r2, rp);
+    const float e0 = floorf(fmaxf(t[0], 0.0f));
+    float G[K - 1];
+#pragma unroll
+    for (int q = 0; q < K - 1; ++q) {
+        const float x = e0 + (float)(q + 1);
+        const float a = __builtin_amdgcn_fmed3f(x - t[0], 0.0f, r1);
+        const float b = __builtin_amdgcn_fmed3f(x - t[1], 0.0f, rp);
+        const float d = __builtin_amdgcn_fmed3f(x - t[2], 0.0f, r2);
+        G[q] = fmaf(a * a, h1, b) + fmaf(-d * h2, d, d);
+    }
+    float wc[K];
+    wc[0] = G[0];
+#pragma unroll
+    for (int q = 1; q < K - 1; ++q)
+        wc[q] = G[q] - G[q - 1];
+    wc[K - 1] = area - G[K - 2];
+    const bool sh = e0 >= 1.0f;
+#pragma unroll
+    for (int q = 0; q <= K; ++q) {
+        const float lo = q >= 1 ? wc[q - 1] : 0.0f, hi = q < K ? wc[q] : 0.0f;
+        wv[q] = val * (sh ? lo : hi);
+    }
+}
+
+// Forward run of slices z0 .. z0 + NS - 1 of one column of a non-circular scan: as sf_fwd_run
+// (running axial integral, one emit per row), with per-voxel transaxial weights, so each row
+// emits K + 1 slot values, one per cell of the run (cells c_lo .. c_lo + K; the run's corners
+// drift by less than one cell).  Face g's interval is [min, max] of its four corners, each
+// expanded as V0 + g (Vs + g Vc) in rows relative to the run's base row edge.  acc0: LDS
+// accumulator of cell c_lo in row 0 (the row has K columns of padding on both sides of the
+// strip, so slots past the strip need no test).  Slices past nz continue on the same lines with
+// zero values (the column tests cover faces up to nz rounded up to NS).
+template <int K, bool INSIDE, int NS>
+__device__ __forceinline__ void nc_fwd_walk(const float (&v)[NS], const float (&T0)[4],
+                                            const float (&ts)[4], const float (&tc)[4],
+                                            const float (&V0)[4], const float (&Vs)[4],
+                                            const float (&Vc)[4], float base, float eps,
+                                            int *acc0, int SW, int R)
+{
+    const float fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
+    // faces by second differences: x_k(g + 1) = x_k(g) + d_k(g), d_k(g + 1) = d_k(g) + 2 Vc_k
+    // (the walk reaches them in order; nothing is formed ahead of time)
+    float fx[4], fd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        fx[k] = V0[k];
+        fd[k] = Vs[k] + Vc[k];
+    }
+    auto face = [&](float &p, float &q) {
+        p = fminf(fminf(fx[0], fx[1]), fminf(fx[2], fx[3]));
+        q = fmaxf(fmaxf(fx[0], fx[1]), fmaxf(fx[2], fx[3]));
+    };
+    auto next_face = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            fx[k] += fd[k];
+            fd[k] = fmaf(2.0f, Vc[k], fd[k]);
+        }
+    };
+    float ft = INSIDE ? 1.0f : fmaxf(base, -1.0f) + 1.0f - base;
+    int *ap = acc0 - SW + __umul24((unsigned)(ft + base), SW);
+    const float lim1 = fR1 - base, limm1 = fRm1 - base;
+    float cp[K + 1], wvc[K + 1], wvp[K + 1];
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        cp[k] = 0.0f;
+        wvp[k] = 0.0f;
+    }
+    auto emit = [&](float al, float be) {
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            const float local = fmaf(wvc[k], al, wvp[k] * be);
+            atomicAdd(ap + k, to_fixed(local - cp[k]));
+            cp[k] = local;
+        }
+        ap += SW;
+        ft += 1.0f;
+    };
+    float pcur, qcur;
+    face(pcur, qcur);
+    float tx[4], td[4];        // transaxial corners of the current voxel, by second differences
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        tx[k] = T0[k];
+        td[k] = ts[k] + tc[k];
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (q > 0) {
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+                wvp[k] = wvc[k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                tx[k] += td[k];
+                td[k] = fmaf(2.0f, tc[k], td[k]);
+            }
+        }
+        nc_slot_weights<K>(tx, v[q], eps, wvc);
+        next_face();
+        float pn, qn;
+        face(pn, qn);
+        const float wq = qcur - pcur;
+        const float h = 0.5f * fast_rcp(fmaxf(wq, 1e-30f));
+        const float fte = INSIDE ? ceilf(pn) - 1.0f : ceilf(fminf(pn, lim1)) - 1.0f;
+        // inside face q or on voxel q's plateau: with u = t - q_q, e = max(u, 0), d2 = e - u,
+        // d1 = w_q - d2, local = wv_q (d1^2 / (2 w_q) + e) - wv_{q-1} d2^2 / (2 w_q)
+        while (ft <= fte) {
+            const float u = ft - qcur, e = fmaxf(u, 0.0f);
+            const float d2 = e - u, d1 = wq - d2;
+            emit(fmaf(d1 * d1, h, e), -(d2 * d2) * h);
+        }
+        // prefix S_{q+1} = S_q + wv_q area_q, area_q = mid_{q+1} - mid_q
+        const float area = 0.5f * ((pn + qn) - (pcur + qcur));
+#pragma unroll
+        for (int k = 0; k <= K; ++k)
+            cp[k] = fmaf(-wvc[k], area, cp[k]);
+        pcur = pn;
+        qcur = qn;
+    }
+    // above the run's top face: the last voxel's falling ramp over face NS
+    {
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            wvp[k] = wvc[k];
+            wvc[k] = 0.0f;
+        }
+        const float h = 0.5f * fast_rcp(fmaxf(qcur - pcur, 1e-30f));
+        const float fte = INSIDE ? floorf(qcur) + 1.0f : floorf(fminf(qcur, limm1)) + 1.0f;
+        while (ft <= fte) {
+            const float d2 = fmaxf(qcur - ft, 0.0f);
+            emit(0.0f, -(d2 * d2) * h);
+        }
+    }
+}
+
+// One run (column col_lane's slices z0 .. z0 + NS - 1) of the non-circular forward pass.
+// rec: the wavefront's staged column records (rec[f][lane]: column index at 0, NU[4] at 1..,
+// DU[4] at 5.., NV[4] at 9.., the amplitude at 13), read here so that they hold no registers
+// during the walk.
+template <int K, bool INSIDE, int NS>
+__device__ __forceinline__ void nc_fwd_item(const float *__restrict__ volb, int64_t colstride,
+                                            int nz, int z0, const float (*rec)[64], int src,
+                                            const NCView &w, float cu, float cvr, float eps,
+                                            int i_lo, int i_hi, int *acc, int SW, int R)
+{
+    const float fR = (float)R;
+    const float z0f = (float)z0;
+    // transaxial corners about slice z0, relative to the run's first cell
+    float T0[4], ts[4], tc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        nc_expand(fmaf(z0f, w.aU, rec[1 + k][src]), fmaf(z0f, w.bW, rec[5 + k][src]), w.aU,
+                  w.bW, T0[k], ts[k], tc[k]);
+    const float o = floorf(T0[0] + cu);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        T0[k] = (T0[k] + cu) - o;
+    const float jl = (float)(NS - 1);
+    const float lo = fminf(T0[0], fmaf(jl, fmaf(jl, tc[0], ts[0]), T0[0]));
+    const float hi = fmaxf(T0[3], fmaf(jl, fmaf(jl, tc[3], ts[3]), T0[3]));
+    const float flo = floorf(lo);
+    const int c_lo = (int)o + (int)flo;
+    const int c_hi = (int)o + (int)floorf(hi);
+    if (c_hi < i_lo || c_lo >= i_hi || c_lo < i_lo - K)
+        return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        T0[k] -= flo;
+    // face corners about face z0, rows relative to the run's base row edge
+    float V0[4], Vs[4], Vc[4];
+    float vmin = 3.0e38f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        nc_expand(fmaf(z0f, w.aV, rec[9 + k][src]),
+                  fmaf(z0f, w.bW, fmaf(-0.5f, w.bW, rec[5 + k][src])), w.aV, w.bW, V0[k], Vs[k],
+                  Vc[k]);
+        V0[k] += cvr;
+        vmin = fminf(vmin, V0[k]);
+    }
+    const float base = floorf(vmin);
+    float vmax = -3.0e38f;
+    const float fn = (float)NS;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        V0[k] -= base;
+        vmax = fmaxf(vmax, fmaf(fn, fmaf(fn, Vc[k], Vs[k]), V0[k]));
+    }
+    if (!INSIDE && (vmax < -base || base >= fR))
+        return;
+    const float amp = rec[13][src];
+    const float *colp = volb + (int64_t)__float_as_int(rec[0][src]) * colstride;
+    float v[NS];
+    if ((nz & 3) == 0 && (NS & 3) == 0) {
+#pragma unroll
+        for (int g = 0; g < NS; g += 4) {
+            const float4 v4 = z0 + g < nz ? *reinterpret_cast<const float4 *>(colp + z0 + g)
+                                          : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            v[g] = v4.x * amp; v[g + 1] = v4.y * amp; v[g + 2] = v4.z * amp; v[g + 3] = v4.w * amp;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            v[q] = z0 + q < nz ? colp[z0 + q] * amp : 0.0f;
+    }
+    nc_fwd_walk<K, INSIDE, NS>(v, T0, ts, tc, V0, Vs, Vc, base, eps, acc + (c_lo - i_lo), SW, R);
+}
+
 // ---- tile culling --------------------------------------------------------------------------
 
 // Detector column range (absolute, cells) that the xy-box [x0,x1] x [y0,y1] (all z) can
@@ -715,6 +1055,16 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
     }
 }
 
+// Non-circular SF forward: column runs of kNCRun slices for footprints of at most 4 cells
+// (the run's cells then fit K + 1 slots), otherwise the per-voxel loop only.
+constexpr int kNCRun = 8;
+template <int GEOM, int METHOD, int K>
+constexpr bool nc_fwd_runs() { return GEOM == kNonCirc && METHOD == kSF && K <= 4 && CTP_FWD_FAST; }
+// Forward LDS row: the strip plus one padding column; the non-circular runs add K columns on
+// each side.
+template <int GEOM, int METHOD, int K>
+constexpr int fwd_row_width() { return kStripW + 1 + (nc_fwd_runs<GEOM, METHOD, K>() ? 2 * K : 0); }
+
 constexpr int kListCap = 2048;
 constexpr int kLaneItems = 32;   // 2D batches up to this size: each lane scatters its own pixel
 
@@ -768,8 +1118,11 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     // map scales), so that they do not occupy registers while the columns are walked
     constexpr bool STAGE = METHOD != kDD && GEOM == kCirc && CTP_FWD_FAST;
     constexpr bool STAGE_DD = METHOD == kDD && GEOM == kCirc && CTP_FWD_FAST;
-    constexpr int kRecFields = STAGE ? 7 + K : STAGE_DD ? 3 + 2 * K : 1;
-    __shared__ float s_colrec[STAGE || STAGE_DD ? kFwdThreads / 64 : 1][kRecFields][64];
+    // non-circular SF column runs (footprints of at most 4 cells): column index, NU[4], DU[4],
+    // NV[4], amplitude, and the lanes of the columns that run
+    constexpr bool STAGE_NC = nc_fwd_runs<GEOM, METHOD, K>();
+    constexpr int kRecFields = STAGE ? 7 + K : STAGE_DD ? 3 + 2 * K : STAGE_NC ? 15 : 1;
+    __shared__ float s_colrec[STAGE || STAGE_DD || STAGE_NC ? kFwdThreads / 64 : 1][kRecFields][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // XCD-aware order: work-group i runs on XCD i % 8; each XCD takes the strips
@@ -789,9 +1142,10 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     const int r0 = chunk * kRowsMax;
     const int R = min(kRowsMax, rows_total - r0);
     const ViewRec V = views[view];
-    constexpr int SW = kStripW + 1;
-
-    int *acc = acc_mem + SW;                 // row -1 (the guard) absorbs emits below row 0
+    constexpr int SW = fwd_row_width<GEOM, METHOD, K>();
+    // row -1 (the guard) absorbs emits below row 0; the non-circular runs also write up to K
+    // cells on either side of the strip (padding columns, never written out)
+    int *acc = acc_mem + SW + (STAGE_NC ? K : 0);
     for (int e = threadIdx.x; e < (R + 1) * SW + kMaxCells; e += blockDim.x)
         acc_mem[e] = 0;
 
@@ -1009,13 +1363,54 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                     }
                 }
             } else if constexpr (METHOD == kSF && GEOM == kNonCirc) {
-                // conservative per-column test over all z, then everything per voxel
+                // conservative per-column test over all z
                 float umin, umax;
                 box_u_range<GEOM, DET>(V, P, xc - 0.5f * P.dx, xc + 0.5f * P.dx,
                                        yc - 0.5f * P.dy, yc + 0.5f * P.dy, umin, umax);
                 const bool hit = valid && umax >= ulo && umin <= uhi;
                 const float amp = sf_amp(V, P, xc, yc);
                 uint64_t m = __ballot(hit);
+                if constexpr (STAGE_NC) {
+                    if (P.nc_runs) {
+                        // columns whose transaxial corner order holds and whose faces are
+                        // disjoint run in runs of kNCRun slices: the (column, run) items of
+                        // all such columns of the tile are spread over the lanes; the other
+                        // columns take the per-voxel loop below
+                        const NCView w = nc_view(V, P);
+                        const int nrun = (P.nz + kNCRun - 1) / kNCRun;
+                        NCCol col;
+                        nc_column(V, P, w, xc, yc, V.cv - (float)r0, R, nrun * kNCRun, col);
+                        const bool ok = hit && col.ok;
+                        const uint64_t m_ok = __ballot(ok);
+                        const bool all_in = __ballot(ok && col.inside) == m_ok;
+                        m &= ~m_ok;
+                        float (*rec)[64] = s_colrec[wave];
+                        rec[0][lane] = __int_as_float(iy * P.nx + ix);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            rec[1 + k][lane] = col.NU[k];
+                            rec[5 + k][lane] = col.DU[k];
+                            rec[9 + k][lane] = col.NV[k];
+                        }
+                        rec[13][lane] = amp;
+                        // lane of the c-th ok column, from the prefix count of the mask
+                        if (ok)
+                            rec[14][__popcll(m_ok & ((1ull << lane) - 1ull))] = __int_as_float(lane);
+                        const int items = (int)__popcll(m_ok) * nrun;
+                        for (int it = lane; it < items; it += 64) {
+                            const int cidx = it / nrun, run = it - cidx * nrun;
+                            const int src = __float_as_int(rec[14][cidx]);
+                            if (all_in)
+                                nc_fwd_item<K, true, kNCRun>(volb, colstride, P.nz, run * kNCRun,
+                                                             rec, src, w, V.cu, V.cv - (float)r0,
+                                                             P.eps, i_lo, i_hi, acc, SW, R);
+                            else
+                                nc_fwd_item<K, false, kNCRun>(volb, colstride, P.nz, run * kNCRun,
+                                                              rec, src, w, V.cu, V.cv - (float)r0,
+                                                              P.eps, i_lo, i_hi, acc, SW, R);
+                        }
+                    }
+                }
                 while (m) {
                     const int c = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1ull;
@@ -1472,6 +1867,172 @@ __device__ __forceinline__ void dd_circ_gather(const Params &P, const float *__r
     }
 }
 
+// Back projection of one view into a lane's kZChunk voxels of a non-circular column: the walk
+// of sf_bwd_fast (running integral of each detector row, one load per row) with the K + 1
+// cells of the chunk carried separately, since the transaxial weights differ per voxel: voxel
+// z gathers sum_k w_k(z) (D_k(z + 1) - D_k(z)).  The corners are expanded about the chunk's
+// first slice and face as in the forward runs.  Returns false, having added nothing, when the
+// chunk's corner orders change, its faces overlap or are wider than a row, or a corner's
+// depth is not positive; the caller then takes the per-voxel path.
+template <int K>
+__device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
+                                             const NCView &w, const float *__restrict__ yv,
+                                             float xc, float yc, int zc0, float amp,
+                                             float (&acc)[kZChunk])
+{
+    constexpr int NQ = kZChunk;
+    const float hx = 0.5f * P.dx, hy = 0.5f * P.dy;
+    const float zc = fmaf((float)zc0, P.dz, P.z0);
+    const float A = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], fmaf(zc, V.eu[2], -V.seu)));
+    const float W = V.sn - fmaf(xc, V.n[0], fmaf(yc, V.n[1], zc * V.n[2]));
+    const float Hf = fmaf(xc, V.ev[0], fmaf(yc, V.ev[1], fmaf(zc - 0.5f * P.dz, V.ev[2], -V.sev)));
+    const float Wf = W - 0.5f * w.bW;
+    const float fq = (float)NQ, jl = (float)(NQ - 1);
+    // transaxial corners about slice zc0 (columns), sorted by u there, with u at the last slice
+    float T0[4], ts[4], tc[4], ke[4];
+    // faces: the corners with the smallest / largest v at face zc0 and at face zc0 + NQ
+    float NVn = 0.0f, DVn = 1.0f, NVx = 0.0f, DVx = 1.0f;
+    float vn0 = 3.0e38f, vx0 = -3.0e38f, vn1 = 3.0e38f, vx1 = -3.0e38f;
+    int in0 = 0, ix0 = 0, in1 = 0, ix1 = 0;
+    float dmin = 3.0e38f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float sx = (k & 1) ? hx : -hx, sy = (k & 2) ? hy : -hy;
+        const float dW = fmaf(sx, V.n[0], sy * V.n[1]);
+        const float DU = W - dW, DV = Wf - dW;
+        dmin = fminf(dmin, fminf(DU, fminf(DV, fmaf(fq, w.bW, DV))));
+        nc_expand(V.Du * fmaf(sx, V.eu[0], fmaf(sy, V.eu[1], A)), DU, w.aU, w.bW, T0[k], ts[k],
+                  tc[k]);
+        T0[k] += V.cu;
+        ke[k] = fmaf(jl, fmaf(jl, tc[k], ts[k]), T0[k]);
+        const float NV = V.Dv * fmaf(sx, V.ev[0], fmaf(sy, V.ev[1], Hf));
+        const float a = fdiv(NV, DV), b = fdiv(fmaf(fq, w.aV, NV), fmaf(fq, w.bW, DV));
+        if (a < vn0) { vn0 = a; in0 = k; NVn = NV; DVn = DV; }
+        if (a > vx0) { vx0 = a; ix0 = k; NVx = NV; DVx = DV; }
+        if (b < vn1) { vn1 = b; in1 = k; }
+        if (b > vx1) { vx1 = b; ix1 = k; }
+    }
+    auto ce = [&](int i, int j) {
+        const bool sw = T0[j] < T0[i];
+        const float a0 = T0[i], a1 = ts[i], a2 = tc[i], a3 = ke[i];
+        T0[i] = sw ? T0[j] : a0; T0[j] = sw ? a0 : T0[j];
+        ts[i] = sw ? ts[j] : a1; ts[j] = sw ? a1 : ts[j];
+        tc[i] = sw ? tc[j] : a2; tc[j] = sw ? a2 : tc[j];
+        ke[i] = sw ? ke[j] : a3; ke[j] = sw ? a3 : ke[j];
+    };
+    ce(0, 1); ce(2, 3); ce(0, 2); ce(1, 3); ce(1, 2);
+    float pa, ps, pc2, qa, qs, qc2;
+    nc_expand(NVn, DVn, w.aV, w.bW, pa, ps, pc2);
+    nc_expand(NVx, DVx, w.aV, w.bW, qa, qs, qc2);
+    pa += V.cv;
+    qa += V.cv;
+    auto pf = [&](int f) { return f == 0 ? pa : fmaf((float)f, fmaf((float)f, pc2, ps), pa); };
+    auto qf = [&](int f) { return f == 0 ? qa : fmaf((float)f, fmaf((float)f, qc2, qs), qa); };
+    const float m = 1e-4f;
+    const bool ok = dmin > 0.0f && ke[0] <= ke[1] && ke[1] <= ke[2] && ke[2] <= ke[3] &&
+                    in0 == in1 && ix0 == ix1 &&
+                    pf(1) - qa >= m && pf(NQ) - qf(NQ - 1) >= m &&      // disjoint, increasing
+                    qa - pa < 1.0f - m && qf(NQ) - pf(NQ) < 1.0f - m;   // narrower than a row
+    if (!ok)
+        return false;
+    // the chunk's cells c_lo .. c_lo + K (its corners drift by less than one cell)
+    const float o = floorf(fminf(fmaxf(fminf(T0[0], ke[0]), -1.0e7f), 1.0e7f));
+    const float hi = fminf(fmaxf(fmaxf(T0[3], ke[3]), -1.0e7f), 1.0e7f);
+    const int c_lo = (int)o;
+    if ((int)floorf(hi) < 0 || c_lo >= P.nu)
+        return true;                       // the whole chunk projects beside the detector
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        T0[k] -= o;
+    const int rows = P.nv;
+    const float p0 = pa, qN = qf(NQ);
+    const bool inside = p0 >= 0.0f && qN < (float)(rows - 2) && c_lo >= 0 && c_lo + K < P.nu;
+    const uint32_t rs = (uint32_t)P.sino_row_stride;
+    uint32_t cidx[K + 1];
+    float cval[K + 1];                     // 1 for cells on the detector, else 0
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        const int cc = c_lo + k;
+        cidx[k] = (uint32_t)min(max(cc, 0), P.nu - 1);
+        cval[k] = (cc >= 0 && cc < P.nu) ? 1.0f : 0.0f;
+    }
+    int jc = inside ? (int)floorf(p0) : (int)floorf(fminf(fmaxf(p0, -1.0f), (float)rows));
+    float nraw[K + 1], rc[K + 1], rp[K + 1], RP[K + 1], D2p[K + 1];
+    auto load_row = [&](int j, float (&dst)[K + 1]) {
+        if (inside) {
+            const float *rp_ = yv + (uint32_t)j * rs + (uint32_t)c_lo;
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+                dst[k] = rp_[k];
+        } else {
+            const bool jv = j >= 0 && j < rows;
+            const uint32_t off = (uint32_t)min(max(j, 0), rows - 1) * rs;
+#pragma unroll
+            for (int k = 0; k <= K; ++k)
+                dst[k] = jv ? yv[off + cidx[k]] * cval[k] : 0.0f;
+        }
+    };
+    load_row(jc, rc);
+    load_row(jc + 1, nraw);
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        rp[k] = 0.0f;
+        RP[k] = 0.0f;
+        D2p[k] = 0.0f;
+    }
+    const float hamp = 0.5f * amp;         // D is carried doubled
+    float tx[4], td[4];      // transaxial corners of the current voxel, by second differences
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        tx[k] = T0[k];
+        td[k] = ts[k] + tc[k];
+    }
+    const float fr = (float)rows;
+#pragma unroll
+    for (int f = 0; f <= NQ; ++f) {
+        const float p = pf(f), q = qf(f), wf = q - p;
+        const int jq = inside ? min((int)floorf(q), rows - 2)
+                              : (int)floorf(fminf(fmaxf(q, -1.0f), fr));
+        while (jc < jq) {
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
+                RP[k] += rc[k];
+                rp[k] = rc[k];
+                rc[k] = nraw[k];
+            }
+            ++jc;
+            load_row(jc + 1, nraw);
+        }
+        const float fjc = (float)jc;
+        const float a = fmaxf(fjc - p, 0.0f);
+        const float aw = (a * a) * fast_rcp(fmaxf(wf, 1e-30f));
+        const float qr = q - fjc;
+        float wv[K + 1];
+        if (f > 0) {
+            nc_slot_weights<K>(tx, hamp, P.eps, wv);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                tx[k] += td[k];
+                td[k] = fmaf(2.0f, tc[k], td[k]);
+            }
+        }
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            const float J2 = fmaf(rp[k] - rc[k], aw, rc[k] * wf);
+            const float D2 = fmaf(2.0f, fmaf(qr, rc[k], RP[k]), -J2);
+            if (f > 0)
+                s = fmaf(wv[k], D2 - D2p[k], s);
+            D2p[k] = D2;
+        }
+        if (f > 0) {
+            acc[f - 1] += s;
+            asm volatile("" : "+v"(acc[f - 1]));
+        }
+    }
+    return true;
+}
+
 // ============================================================================================
 // Back projector
 // ============================================================================================
@@ -1558,7 +2119,12 @@ __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_ker
                 }
             } else if constexpr (METHOD == kSF && GEOM == kNonCirc) {
                 const float amp = sf_amp(V, P, xc, yc);
-#pragma unroll
+                if constexpr (nc_fwd_runs<GEOM, METHOD, K>()) {
+                    if (P.nc_runs && nc_bwd_chunk<K>(V, P, nc_view(V, P), yv, xc, yc, zc0, amp, acc))
+                        continue;
+                }
+                // per-voxel path, kept rolled (see sf_circ_gather)
+#pragma unroll 1
                 for (int q = 0; q < kZChunk; ++q) {
                     const int z = zc0 + q;
                     if (z < nzv) {
@@ -1583,7 +2149,9 @@ __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_ker
                                         rs = fmaf(w[k], yr[k], rs);
                                 s = fmaf(F, rs, s);
                             });
-                            acc[q] += s;
+#pragma unroll
+                            for (int qq = 0; qq < kZChunk; ++qq)
+                                acc[qq] += qq == q ? s : 0.0f;
                         }
                     }
                 }
@@ -1761,7 +2329,7 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
 {
     const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
     const int R = min(kRowsMax, rows_total);
-    size_t lds = ((size_t)(R + 1) * (kStripW + 1) + kMaxCells) * sizeof(int);
+    size_t lds = ((size_t)(R + 1) * fwd_row_width<GEOM, METHOD, K>() + kMaxCells) * sizeof(int);
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
     dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.n_views),
               (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);

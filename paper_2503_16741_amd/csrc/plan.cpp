@@ -197,6 +197,9 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dy, hz = two_d ? 0.0 : 0.5 * nz * g.dz;
     std::vector<ctp::ViewRec> recs((size_t)g.n_views);
     double kmax = 0.0;   // widest transaxial footprint (columns) over all views
+    // non-circular SF column runs: remainder of the second-order expansion of a corner's
+    // projection over a run, and how far a footprint drifts along a run (columns)
+    double nc_rem = 0.0, nc_drift = 0.0;
     double rmax = 0.0;   // recon mode: largest SAD / W over views and volume corners
     double mmin = 1e300; // smallest magnification over views and volume corners
 
@@ -222,13 +225,14 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         f.ve0 = two_d ? -0.5 * g.dv : -0.5 * nv * g.dv - vo.at(b);
 
         // every corner of the volume box must lie strictly in front of the source
-        double Wmin = 1e300, Wmax = 0.0, amax = 0.0;
+        double Wmin = 1e300, Wmax = 0.0, amax = 0.0, vmax = 0.0;
         for (int c = 0; c < 8; ++c) {
             const Vec3 p{(c & 1) ? hx : -hx, (c & 2) ? hy : -hy, (c & 4) ? hz : -hz};
             const double W = dot(f.s - p, f.n);
             Wmin = std::fmin(Wmin, W);
             Wmax = std::fmax(Wmax, W);
             amax = std::fmax(amax, std::fabs(dot(p - f.s, f.eu)));
+            vmax = std::fmax(vmax, std::fabs(dot(p - f.s, f.ev)));
         }
         const double D = dot(f.s - f.d, f.n);
         if (!(Wmin > 1e-6 * f.sdd))
@@ -241,6 +245,19 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
                                                   : f.sdd / Wmin / g.du;
         const double ext = method == CTP_SF ? std::sqrt(g.dx * g.dx + g.dy * g.dy) : std::fmax(g.dx, g.dy);
         kmax = std::fmax(kmax, grad * ext);
+        if (g.kind == CTP_CONE_NONCIRC && Wmin > 0.0) {
+            // along a column a corner projects to f(j) = f0 + s j / (1 + r j) (j: slices from
+            // a run's start) with r = dz n_z / W and |s| at most as below; the kernels use
+            // f0 + s j (1 - r j), off by |s| r^2 j^3
+            const double Du = (g.det == CTP_DET_FLAT ? D : f.sdd) / g.du;
+            const double Dv = (g.det == CTP_DET_FLAT ? D : f.sdd) / g.dv;
+            const double r = g.dz * std::fabs(f.n.z) / Wmin;
+            const double su = Du * g.dz * (std::fabs(f.eu.z) + amax / Wmin * std::fabs(f.n.z)) / Wmin;
+            const double sv = Dv * g.dz * (std::fabs(f.ev.z) + vmax / Wmin * std::fabs(f.n.z)) / Wmin;
+            const double j = ctp::kNCRunMax;
+            nc_rem = std::fmax(nc_rem, std::fmax(su, sv) * r * r * j * j * j);
+            nc_drift = std::fmax(nc_drift, su * (j - 1.0));
+        }
 
         ctp::ViewRec &r = recs[(size_t)b];
         std::memset(&r, 0, sizeof(r));
@@ -362,6 +379,12 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     p.dv = (float)(two_d ? 1.0 : g.dv);
     p.n_views = g.n_views;
     p.eps = 1e-6f;
+    // non-circular SF column runs: expansion accurate to 2e-5 cells / rows, a run's footprints
+    // within K + 1 cells (their union is narrower than K: widths below K - 1 plus the drift)
+    // and the drift below one cell
+    p.nc_runs = (g.kind == CTP_CONE_NONCIRC && method == CTP_SF && !recon && c.kcells <= 4 &&
+                 nc_rem < 2e-5 && nc_drift < 0.999 && (kmax + nc_drift) * 1.001 < c.kcells)
+                    ? 1 : 0;
     plan->g.theta = plan->g.phi = plan->g.psi = plan->g.sad = plan->g.sdd = nullptr;
     plan->g.x_src = plan->g.z_src = plan->g.x_ofst = plan->g.y_ofst = plan->g.z_ofst = nullptr;
     plan->g.u_ofst = plan->g.v_ofst = nullptr;
