@@ -495,6 +495,7 @@ __device__ __forceinline__ void nc_expand(float N0, float D0, float a, float b, 
 struct NCCol {
     float NU[4], DU[4], NV[4];
     bool ok, inside;
+    int r_lo, r_hi;   // runs whose footprints may meet the strip (r_lo > r_hi: none)
 };
 
 // v-interval [p, q] (rows, without cv) of face f of a column (corners NV, DU as in NCCol).
@@ -511,11 +512,13 @@ __device__ __forceinline__ void nc_face(const float (&NV)[4], const float (&DU)[
     }
 }
 
-// nf: the faces the runs walk (the slices rounded up to whole runs); cvr: V.cv minus the row
-// window's first row; R: rows in the window.
+// nf: the faces the runs walk (the slices rounded up to whole runs of NS); cvr: V.cv minus the
+// row window's first row; R: rows in the window; [ulo, uhi]: the strip's columns (absolute,
+// with a margin), against which the runs are selected.
+template <int NS>
 __device__ __forceinline__ void nc_column(const ViewRec &V, const Params &P, const NCView &w,
                                           float xc, float yc, float cvr, int R, int nf,
-                                          NCCol &c)
+                                          float ulo, float uhi, NCCol &c)
 {
     const float hx = 0.5f * P.dx, hy = 0.5f * P.dy;
     const float A0 = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], fmaf(P.z0, V.eu[2], -V.seu)));
@@ -557,6 +560,30 @@ __device__ __forceinline__ void nc_column(const ViewRec &V, const Params &P, con
     const float m = 1e-4f;
     c.ok = dmin > 0.0f && tstable && p1 - q0 >= m && pn - ql >= m;
     c.inside = p0 + cvr >= 0.0f && qn + cvr < (float)(R - 1);
+    // Runs that can meet the strip: the footprint's ends t0, t3 are close to affine along the
+    // column (the second-order term stays below a few hundredths of a cell over a column), so
+    // the slices where [t0, t3] overlaps [ulo, uhi] (widened by 0.25 cells) form one interval.
+    // Each run still tests its own cells exactly.
+    const float zlast = zl > 0.0f ? zl : 1.0f;
+    const float lo0 = k0[0] + V.cu, lo1 = k1[0] + V.cu, hi0 = k0[3] + V.cu, hi1 = k1[3] + V.cu;
+    const float a = ulo - 0.25f, b = uhi + 0.25f;
+    // z with hi(z) >= a and lo(z) <= b, hi and lo linear between slice 0 and slice zl
+    float zmin = 0.0f, zmax = zl;
+    const float dh = (hi1 - hi0) / zlast, dl = (lo1 - lo0) / zlast;
+    if (dh > 0.0f) zmin = fmaxf(zmin, (a - hi0) / dh);
+    else if (dh < 0.0f) zmax = fminf(zmax, (a - hi0) / dh);
+    else if (hi0 < a) zmax = -1.0f;
+    if (dl > 0.0f) zmax = fminf(zmax, (b - lo0) / dl);
+    else if (dl < 0.0f) zmin = fmaxf(zmin, (b - lo0) / dl);
+    else if (lo0 > b) zmax = -1.0f;
+    const int nrun = nf / NS;
+    if (!(zmin <= zmax)) {
+        c.r_lo = 0;
+        c.r_hi = -1;
+    } else {
+        c.r_lo = max((int)floorf(zmin / (float)NS) - 1, 0);
+        c.r_hi = min((int)floorf(zmax / (float)NS) + 1, nrun - 1);
+    }
 }
 
 // Slot weights of one voxel of a run: its transaxial corners t_k (columns relative to the run's
@@ -656,11 +683,15 @@ __device__ __forceinline__ void nc_fwd_walk(const float (&v)[NS], const float (&
     };
     float pcur, qcur;
     face(pcur, qcur);
-    float tx[4], td[4];        // transaxial corners of the current voxel, by second differences
+    // transaxial corners of the current voxel by second differences, with the corners' mean
+    // second-order coefficient (they differ by a relative 2 |dW| / W; the transaxial slopes are
+    // small, so this moves a corner by far less than the expansion's own remainder)
+    const float tc2 = 0.5f * ((tc[0] + tc[1]) + (tc[2] + tc[3]));
+    float tx[4], td[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         tx[k] = T0[k];
-        td[k] = ts[k] + tc[k];
+        td[k] = ts[k] + 0.5f * tc2;
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
@@ -671,7 +702,7 @@ __device__ __forceinline__ void nc_fwd_walk(const float (&v)[NS], const float (&
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 tx[k] += td[k];
-                td[k] = fmaf(2.0f, tc[k], td[k]);
+                td[k] += tc2;
             }
         }
         nc_slot_weights<K>(tx, v[q], eps, wvc);
@@ -1065,7 +1096,7 @@ constexpr bool nc_fwd_runs() { return GEOM == kNonCirc && METHOD == kSF && K <= 
 template <int GEOM, int METHOD, int K>
 constexpr int fwd_row_width() { return kStripW + 1 + (nc_fwd_runs<GEOM, METHOD, K>() ? 2 * K : 0); }
 
-constexpr int kListCap = 2048;
+constexpr int kListCap = 1024;
 constexpr int kLaneItems = 32;   // 2D batches up to this size: each lane scatters its own pixel
 
 // 2D forward with a small batch: lane = pixel, looping over the batch items itself (the
@@ -1097,7 +1128,7 @@ constexpr int kFwdThreads = CTP_FWD_THREADS;
 constexpr int kFwdWaves = kFwdThreads / 64;
 
 template <int GEOM, int DET, int METHOD, int K>
-__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4))) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
                                                   const float *__restrict__ volT,
                                                   const float *__restrict__ qscale,
                                                   float *__restrict__ sino, int accumulate,
@@ -1119,9 +1150,9 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
     constexpr bool STAGE = METHOD != kDD && GEOM == kCirc && CTP_FWD_FAST;
     constexpr bool STAGE_DD = METHOD == kDD && GEOM == kCirc && CTP_FWD_FAST;
     // non-circular SF column runs (footprints of at most 4 cells): column index, NU[4], DU[4],
-    // NV[4], amplitude, and the lanes of the columns that run
+    // NV[4], amplitude, and per column that runs: its lane and first item, its first run
     constexpr bool STAGE_NC = nc_fwd_runs<GEOM, METHOD, K>();
-    constexpr int kRecFields = STAGE ? 7 + K : STAGE_DD ? 3 + 2 * K : STAGE_NC ? 15 : 1;
+    constexpr int kRecFields = STAGE ? 7 + K : STAGE_DD ? 3 + 2 * K : STAGE_NC ? 16 : 1;
     __shared__ float s_colrec[STAGE || STAGE_DD || STAGE_NC ? kFwdThreads / 64 : 1][kRecFields][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1379,7 +1410,8 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                         const NCView w = nc_view(V, P);
                         const int nrun = (P.nz + kNCRun - 1) / kNCRun;
                         NCCol col;
-                        nc_column(V, P, w, xc, yc, V.cv - (float)r0, R, nrun * kNCRun, col);
+                        nc_column<kNCRun>(V, P, w, xc, yc, V.cv - (float)r0, R, nrun * kNCRun,
+                                          (float)i_lo, (float)i_hi, col);
                         const bool ok = hit && col.ok;
                         const uint64_t m_ok = __ballot(ok);
                         const bool all_in = __ballot(ok && col.inside) == m_ok;
@@ -1393,21 +1425,55 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(Params P, const ViewRe
                             rec[9 + k][lane] = col.NV[k];
                         }
                         rec[13][lane] = amp;
-                        // lane of the c-th ok column, from the prefix count of the mask
-                        if (ok)
-                            rec[14][__popcll(m_ok & ((1ull << lane) - 1ull))] = __int_as_float(lane);
-                        const int items = (int)__popcll(m_ok) * nrun;
-                        for (int it = lane; it < items; it += 64) {
-                            const int cidx = it / nrun, run = it - cidx * nrun;
-                            const int src = __float_as_int(rec[14][cidx]);
-                            if (all_in)
+                        // the (column, run) items of the runs that can meet the strip: the
+                        // ok columns in lane order, each with its first run and its first
+                        // item (an exclusive prefix sum of the run counts over the lanes)
+                        const int nr = ok ? max(col.r_hi - col.r_lo + 1, 0) : 0;
+                        int incl = nr;
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1) {
+                            const int t = __shfl_up(incl, d);
+                            if (lane >= d)
+                                incl += t;
+                        }
+                        const int items = __shfl(incl, 63);
+                        if (ok) {
+                            const int j = (int)__popcll(m_ok & ((1ull << lane) - 1ull));
+                            rec[14][j] = __int_as_float(lane | ((incl - nr) << 6));
+                            rec[15][j] = __int_as_float(col.r_lo);
+                        }
+                        const int n_ok = (int)__popcll(m_ok);
+                        // item it: the last ok column whose first item is at most it
+                        auto item = [&](int it, int &src, int &run) {
+                            int jl = 0, jh = n_ok - 1;
+                            while (jl < jh) {
+                                const int jm = (jl + jh + 1) >> 1;
+                                if ((__float_as_int(rec[14][jm]) >> 6) <= it)
+                                    jl = jm;
+                                else
+                                    jh = jm - 1;
+                            }
+                            const int e = __float_as_int(rec[14][jl]);
+                            src = e & 63;
+                            run = __float_as_int(rec[15][jl]) + (it - (e >> 6));
+                        };
+                        // one loop per specialisation keeps the two walks' registers apart
+                        if (all_in) {
+                            for (int it = lane; it < items; it += 64) {
+                                int src, run;
+                                item(it, src, run);
                                 nc_fwd_item<K, true, kNCRun>(volb, colstride, P.nz, run * kNCRun,
                                                              rec, src, w, V.cu, V.cv - (float)r0,
                                                              P.eps, i_lo, i_hi, acc, SW, R);
-                            else
+                            }
+                        } else {
+                            for (int it = lane; it < items; it += 64) {
+                                int src, run;
+                                item(it, src, run);
                                 nc_fwd_item<K, false, kNCRun>(volb, colstride, P.nz, run * kNCRun,
                                                               rec, src, w, V.cu, V.cv - (float)r0,
                                                               P.eps, i_lo, i_hi, acc, SW, R);
+                            }
                         }
                     }
                 }
@@ -1981,11 +2047,14 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         D2p[k] = 0.0f;
     }
     const float hamp = 0.5f * amp;         // D is carried doubled
-    float tx[4], td[4];      // transaxial corners of the current voxel, by second differences
+    // transaxial corners of the current voxel by second differences, with the corners' mean
+    // second-order coefficient (as in the forward runs)
+    const float tc2 = 0.5f * ((tc[0] + tc[1]) + (tc[2] + tc[3]));
+    float tx[4], td[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         tx[k] = T0[k];
-        td[k] = ts[k] + tc[k];
+        td[k] = ts[k] + 0.5f * tc2;
     }
     const float fr = (float)rows;
 #pragma unroll
@@ -2013,7 +2082,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 tx[k] += td[k];
-                td[k] = fmaf(2.0f, tc[k], td[k]);
+                td[k] += tc2;
             }
         }
         float s = 0.0f;

@@ -248,14 +248,17 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         if (g.kind == CTP_CONE_NONCIRC && Wmin > 0.0) {
             // along a column a corner projects to f(j) = f0 + s j / (1 + r j) (j: slices from
             // a run's start) with r = dz n_z / W and |s| at most as below; the kernels use
-            // f0 + s j (1 - r j), off by |s| r^2 j^3
+            // f0 + s j + c j^2 (c = -s r), off by |s| r^2 j^3; the transaxial corners share
+            // the mean of their four c, which lie within 2 |dW| / W of it (dW: a corner's depth
+            // offset from the column centre)
             const double Du = (g.det == CTP_DET_FLAT ? D : f.sdd) / g.du;
             const double Dv = (g.det == CTP_DET_FLAT ? D : f.sdd) / g.dv;
             const double r = g.dz * std::fabs(f.n.z) / Wmin;
             const double su = Du * g.dz * (std::fabs(f.eu.z) + amax / Wmin * std::fabs(f.n.z)) / Wmin;
             const double sv = Dv * g.dz * (std::fabs(f.ev.z) + vmax / Wmin * std::fabs(f.n.z)) / Wmin;
             const double j = ctp::kNCRunMax;
-            nc_rem = std::fmax(nc_rem, std::fmax(su, sv) * r * r * j * j * j);
+            const double dwr = std::hypot(g.dx, g.dy) / Wmin;
+            nc_rem = std::fmax(nc_rem, std::fmax(su * (r * j + dwr), sv * r * j) * r * j * j);
             nc_drift = std::fmax(nc_drift, su * (j - 1.0));
         }
 

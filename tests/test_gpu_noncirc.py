@@ -51,8 +51,9 @@ def rot(theta, phi, psi):
 
 
 def run_regime(g, run=16):
-    """The plan's condition for the column runs, restated: second-order remainder below 2e-5
-    cells / rows, drift along a run below one cell, widest footprint plus drift below K."""
+    """The plan's condition for the column runs, restated: second-order remainder (with the
+    corners' shared second-order coefficient) below 2e-5 cells / rows, drift along a run below
+    one cell, widest footprint plus drift below K."""
     hx, hy, hz = g.nx * g.dx / 2, g.ny * g.dy / 2, g.nz * g.dz / 2
     kmax = rem = drift = 0.0
     for b in range(g.n_views):
@@ -73,7 +74,8 @@ def run_regime(g, run=16):
         r = g.dz * abs(n[2]) / wmin
         su = D / g.du * g.dz * (abs(eu[2]) + amax / wmin * abs(n[2])) / wmin
         sv = D / g.dv * g.dz * (abs(ev[2]) + vmax / wmin * abs(n[2])) / wmin
-        rem = max(rem, max(su, sv) * r * r * run ** 3)
+        dwr = math.hypot(g.dx, g.dy) / wmin
+        rem = max(rem, max(su * (r * run + dwr), sv * r * run) * r * run ** 2)
         drift = max(drift, su * (run - 1))
     need = math.floor(kmax * 1.001 + 1e-6) + 2
     K = 3 if need <= 3 else 4 if need <= 4 else 8
