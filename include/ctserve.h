@@ -21,7 +21,9 @@
  *     plan, direction and storage types (at most max_batch, in arrival order; the paper's
  *     batched, channelled tensors, Section 1 and 2.4: one plan serves the whole batch).  If the
  *     merged call does not fit, fewer requests are merged.
- *   - Overlap.  Each slot owns a HIP stream; up to n_slots calls run concurrently.
+ *   - Overlap.  Each slot owns a HIP stream; up to n_slots calls run concurrently.  Optionally
+ *     the last slot is an express lane for short requests (express_work below): it never takes
+ *     a long call, and the other slots still take short ones.
  *
  * Results are those of ctp_project / ctp_backproject with batch = the merged count.  Every
  * batch item's result is bitwise independent of the other items of its call (the forward
@@ -52,6 +54,11 @@ typedef struct {
     int32_t max_batch;    /* most requests merged into one call, 1..1024 */
     int64_t age_cap_us;   /* wait after which a request is served in arrival order (>= 0;
                              0 = strict first come, first served) */
+    double express_work;  /* with n_slots >= 2 and express_work > 0, the last slot runs only
+                             calls whose requests' work (voxel-view updates) is at most this,
+                             and merges at most express_work of it into one call, so short
+                             requests never wait behind a device full of long calls;
+                             0 = every slot takes every call */
 } ctp_server_config;
 
 /* Host-clock times (steady clock, ns) and placement of one request. */

@@ -88,6 +88,7 @@ struct ctp_server {
     char *arena = nullptr;
     int max_batch = 1;
     int64_t age_cap_ns = 0;             // 0: strict first come, first served
+    double express_work = 0.0;          // > 0: the last slot takes only calls this short
     std::vector<Slot> slots;
 
     std::mutex mu;
@@ -111,12 +112,9 @@ struct ctp_server {
             n += s.batch ? 1 : 0;
         return n;
     }
-    int free_slot() const
+    bool is_express(int slot) const
     {
-        for (size_t i = 0; i < slots.size(); ++i)
-            if (!slots[i].batch)
-                return (int)i;
-        return -1;
+        return express_work > 0.0 && slots.size() >= 2 && slot == (int)slots.size() - 1;
     }
     void free_batch_scratch(Batch &b)
     {
@@ -191,13 +189,18 @@ struct ctp_server {
     // head that does not fit is passed over; an aged one is not (the memory that frees up is
     // kept for it), so no request waits behind later ones for longer than the cap.  Returns an
     // empty pointer if nothing may start now.
+    // The express slot considers only short requests, and an aged long request does not hold
+    // it (it can never run there).
     std::shared_ptr<Batch> admit(int slot)
     {
         size_t n_aged = 0;
         const std::vector<size_t> order = ctp::head_order(
             queue, now_ns(), age_cap_ns,
             [](const Request *r) { return std::make_pair(r->work, r->t_submit); }, &n_aged);
+        const bool express = is_express(slot);
         for (size_t k = 0; k < order.size(); ++k) {
+            if (express && queue[order[k]]->work > express_work)
+                continue;
             std::shared_ptr<Batch> b = try_admit(order[k], slot);
             if (b || k < n_aged)
                 return b;
@@ -208,7 +211,11 @@ struct ctp_server {
     // Reserve a call headed by queue[head_pos] with as many of its batch candidates as fit.
     std::shared_ptr<Batch> try_admit(size_t head_pos, int slot)
     {
-        std::vector<size_t> pos = ctp::batch_candidates(queue, head_pos, max_batch, key_of);
+        // a call on the express slot stays short: at most express_work in all
+        int cap = max_batch;
+        if (is_express(slot) && queue[head_pos]->work > 0.0)
+            cap = std::max(1, (int)std::min((double)max_batch, express_work / queue[head_pos]->work));
+        std::vector<size_t> pos = ctp::batch_candidates(queue, head_pos, cap, key_of);
         const Request *head = queue[head_pos];
         for (int64_t n = (int64_t)pos.size(); n >= 1; --n) {
             size_t ws = 0;
@@ -335,10 +342,18 @@ struct ctp_server {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             poll();
-            for (int slot = free_slot(); slot >= 0 && !queue.empty(); slot = free_slot()) {
-                std::shared_ptr<Batch> b = admit(slot);
-                if (!b)
-                    break;
+            // free slots in order (the express slot, the last, after the others): each takes
+            // the next call it may run; when a regular slot can start nothing, no other regular
+            // slot can, and only the express slot is still tried
+            for (size_t slot = 0; slot < slots.size() && !queue.empty(); ++slot) {
+                if (slots[slot].batch)
+                    continue;
+                std::shared_ptr<Batch> b = admit((int)slot);
+                if (!b) {
+                    if (express_work > 0.0 && slots.size() >= 2 && slot + 1 < slots.size() - 1)
+                        slot = slots.size() - 2;       // next: the express slot
+                    continue;
+                }
                 lk.unlock();
                 std::string msg;
                 const bool ok = launch(*b, msg);
@@ -405,6 +420,8 @@ ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out)
         return ctp::set_error(CTP_EINVAL, "max_batch must be in 1..1024");
     if (cfg->age_cap_us < 0)
         return ctp::set_error(CTP_EINVAL, "age_cap_us must be >= 0");
+    if (!(cfg->express_work >= 0.0))
+        return ctp::set_error(CTP_EINVAL, "express_work must be >= 0");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess)
         return ctp::set_error(CTP_EDEVICE, "no HIP device");
@@ -415,6 +432,7 @@ ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out)
     s->arena = static_cast<char *>(cfg->arena);
     s->max_batch = cfg->max_batch;
     s->age_cap_ns = cfg->age_cap_us * 1000;
+    s->express_work = cfg->express_work;
     s->alloc.reset(cfg->arena_bytes);
     s->slots.resize((size_t)cfg->n_slots);
     for (Slot &sl : s->slots) {

@@ -216,8 +216,11 @@ static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, i
         r.out = rng() % 10 < 7 ? r.in : CTP_F32;
         reqs.push_back(r);
     }
+    // odd seeds: strict arrival order; even: age cap 20 ms; every third seed with two or more
+    // slots also reserves the last slot for the small plans
+    const double express = (seed % 3 == 0 && slots >= 2) ? 100.0 : 0.0;   // plan_work: us per item
     ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch,
-                          seed % 2 ? 0 : 20000};
+                          seed % 2 ? 0 : 20000, express};
     ctp_server *srv = nullptr;
     CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
     static char dummy_input[16];
@@ -254,10 +257,11 @@ static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, i
     CHECK(ctp_server_destroy(srv) == CTP_OK);
 }
 
-static ctp_server *make_server(size_t arena_bytes, int slots, int max_batch, int64_t age_cap_us)
+static ctp_server *make_server(size_t arena_bytes, int slots, int max_batch, int64_t age_cap_us,
+                               double express_work = 0.0)
 {
     ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch,
-                          age_cap_us};
+                          age_cap_us, express_work};
     ctp_server *srv = nullptr;
     CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
     return srv;
@@ -419,6 +423,50 @@ static void ordering()
     }
 }
 
+// Express slot: with a two-slot server whose last slot takes only short requests, short requests
+// that arrive behind a queue of long calls run at once on the express slot (they finish before
+// the second long call starts), while the long calls keep the other slot; a long request never
+// runs on the express slot.
+static void express_slot()
+{
+    ctp_plan big, small;
+    big.nvox = 32 * 32 * 32; big.ncell = 20 * 40 * 40; big.us_per_item = 20000;
+    small.nvox = 8 * 8 * 8; small.ncell = 4 * 10 * 10; small.us_per_item = 200;
+    static char dummy_input[16];
+    const double small_work = ctp::plan_work(&small);
+    ctp_server *srv = make_server(256u << 20, 2, 1, 0, small_work);
+    std::vector<uint64_t> bigs, smalls;
+    for (int i = 0; i < 3; ++i) {
+        uint64_t t = 0;
+        CHECK(ctp_server_submit(srv, &big, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+        bigs.push_back(t);
+    }
+    wait_running(srv, bigs[0]);
+    for (int i = 0; i < 4; ++i) {
+        uint64_t t = 0;
+        CHECK(ctp_server_submit(srv, &small, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+        smalls.push_back(t);
+    }
+    for (uint64_t t : bigs)
+        CHECK(ctp_server_wait(srv, t, 20 * 1000 * 1000, nullptr) == CTP_OK);
+    for (uint64_t t : smalls)
+        CHECK(ctp_server_wait(srv, t, 20 * 1000 * 1000, nullptr) == CTP_OK);
+    ctp_request_info b1{}, b2{};
+    CHECK(ctp_server_info(srv, bigs[1], &b1) == CTP_OK);
+    CHECK(ctp_server_info(srv, bigs[2], &b2) == CTP_OK);
+    CHECK(b1.slot == 0 && b2.slot == 0);                // long calls never take the express slot
+    for (uint64_t t : smalls) {
+        ctp_request_info si{};
+        CHECK(ctp_server_info(srv, t, &si) == CTP_OK);
+        CHECK(si.done_ns < b1.admit_ns || si.slot == 1);   // ran beside the first long call
+        CHECK(si.done_ns < b2.admit_ns);
+    }
+    std::vector<uint64_t> all(bigs);
+    all.insert(all.end(), smalls.begin(), smalls.end());
+    release_all_and_drain(srv, all);
+    CHECK(ctp_server_destroy(srv) == CTP_OK);
+}
+
 int main()
 {
     // the configuration of the GPU serving test, then tighter arenas and other slot counts
@@ -434,6 +482,7 @@ int main()
         failure_injection(seed);
     cancellation();
     ordering();
+    express_slot();
     std::printf("ok\n");
     return 0;
 }

@@ -60,12 +60,19 @@ def make_input(torch, geom, direction, dtype, seed):
     return torch.from_numpy(a).cuda().to(dtype).contiguous()
 
 
-def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc):
+@pytest.mark.parametrize("n_slots,express", [(2, False), (3, True)])
+def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc, n_slots, express):
+    """Every result of a mixed burst equals the direct batch-1 call bit for bit; with an
+    express slot (the last one, for the small kinds only) the long calls never run there."""
     torch = torch_gpu
     from paper_2503_16741_amd import ctproj
     geo = geometries()
     plans = {k: make_plan(ctproj, e) for k, e in geo.items()}
-    srv = ctproj.Server(256 << 20, n_slots=2, max_batch=6)
+    work = {k: float(e[0].n_vox) * e[0].n_views for k, e in geo.items()}
+    small_work = max(w for k, w in work.items() if k != "big")
+    assert small_work < work["big"]
+    srv = ctproj.Server(256 << 20, n_slots=n_slots, max_batch=6,
+                        express_work=small_work if express else 0.0)
     rng = np.random.default_rng(42)
     reqs = []
     # four long calls first (two run, two wait), so that the burst behind them queues and
@@ -100,6 +107,9 @@ def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc):
     assert any(i["batch"] > 1 for i in infos)
     for i in infos:
         assert i["submit_ns"] <= i["admit_ns"] <= i["done_ns"]
+    if express:
+        assert all(i["slot"] != n_slots - 1 for r, i in zip(reqs, infos) if r[0] == "big")
+        assert any(i["slot"] == n_slots - 1 for i in infos)
     # bitwise: alone (batch 1, direct call) == in the mix
     for (k, d, dt, odt, seed), x, y in zip(reqs, inputs, served):
         ref = alone(ctproj, plans[k], d, x, odt)
