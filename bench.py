@@ -7,9 +7,11 @@ synthetic ellipsoid phantom, 256^3 voxels at 0.5 mm, 360 views over 360 deg, fla
 voxel x view updates per second over the pair, GUPS = 2 * N_vox * N_view / t_pair, with p50/p99
 pair latency.  Prints one JSON line.
 
-The dominant kernel's roofline uses an algorithmic FP32 operation count per voxel-view of the
-SF-TT method (constants below, measured footprint statistics from the CPU oracle) against the
-chip's FP32 VALU issue rate; the CPU baseline times the FP64 oracle on a bounded sample.
+The dominant kernel's roofline is the VALU issue rate: the VALU instructions that kernel executes
+per launch (rocprofv3 SQ_INSTS_VALU, committed under profiles/ for the current kernel source)
+times 64 lanes, over its measured time, against the chip's FP32 VALU rate; the algorithmic
+operation count of the SF-TT method is reported beside it.  The CPU baseline times the FP64
+oracle on a bounded sample and attaches the whole-scan runs from profiles/.
 """
 import argparse
 import hashlib
@@ -32,11 +34,10 @@ METRIC = "GUPS (voxel×view updates/s) SF fwd+back at 256³×360 views; p99 late
 SF_ROWS_PER_VV = 2.007
 SF_NNZ_PER_VV = 4.461
 SF_OPS_PER_VV = 4 + 6 + 10 + 13 * (SF_ROWS_PER_VV - 1) + SF_ROWS_PER_VV + 2 * SF_NNZ_PER_VV + 0.4
-# FP32 VALU peak: the published 157.3 TFLOP/s is 128 FP32 lanes per clock per CU (an FMA being
-# two flops), i.e. 256 CU x 128 x 2.4 GHz = 78.6e12 FP32 operations per second counting an
-# FMA, add, multiply or min/max as one operation -- the unit of the count above.  (A dependent
-# v_fma_f32 chain sustains half of that; two-operand v_fmac_f32 streams sustain more than half,
-# measured 42e12/s in the ramp filter.)
+# FP32 VALU peak: the published 157.3 TFLOP/s is 256 CUs x 128 FP32 lanes per clock x 2.4 GHz,
+# an FMA counting two flops: 78.6e12 VALU lane-instructions per second (each SIMD completes a
+# wave64 FP32 instruction every two clocks).  The counters confirm the lane rate: the kernels
+# here execute 46-52e12 lane-instructions per second, above the 39.3e12 of 64 lanes per clock.
 VALU_PEAK = 256 * 128 * 2.4e9
 HBM_PEAK = 8.0e12
 
@@ -56,7 +57,21 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_name):
+def load_counters(probe, kernel_key):
+    """VALU instructions (wave64) per launch of one kernel from profiles/counters.json, if the
+    counters were taken on the current kernel source."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != kernel_hash():
+        return None
+    k = c.get(probe, {}).get(kernel_key)
+    return None if k is None else k["raw"].get("SQ_INSTS_VALU")
+
+
+def load_traffic(kernel_name, probe="sf_c2"):
     """HBM bytes per launch from the committed PMC summary, if it was taken on this source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -66,7 +81,7 @@ def load_traffic(kernel_name):
         return None
     if t.get("source_hash") != kernel_hash():
         return None
-    k = t.get("kernels", {}).get(kernel_name)
+    k = t.get("probes", {}).get(probe, {}).get("kernels", {}).get(kernel_name)
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -75,11 +90,11 @@ KERNEL_KEYS = {"fwd_kernel": "sf_forward", "bwd_kernel": "sf_backward",
                "item_max_kernel": "item_max"}
 
 
-def summarize_traffic(fetch_csv, write_csv):
-    """Turn two rocprofv3 --pmc runs of `bench.py --traffic-probe` (FETCH_SIZE, WRITE_SIZE; KiB
+def summarize_traffic(fetch_csv, write_csv, probe="sf_c2"):
+    """Turn two rocprofv3 --pmc runs of `bench.py --probe <probe>` (FETCH_SIZE, WRITE_SIZE; KiB
     per dispatch) into HBM bytes per launch, calibrated by the 512 MiB device copy in the same
-    run (bytes read and written by that copy are known).  Writes profiles/traffic.json and
-    profiles/traffic_sf_c2.md."""
+    run (bytes read and written by that copy are known).  Adds the probe to
+    profiles/traffic.json and writes profiles/traffic_<probe>.md."""
     import csv
     import collections
 
@@ -98,20 +113,20 @@ def summarize_traffic(fetch_csv, write_csv):
     f_copy = [v for n, v in fetch if "copyBuffer" in n][0] * 1024
     w_copy = [v for n, v in write if "copyBuffer" in n][0] * 1024
     f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
-    out = {"source_hash": kernel_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
-           "kernels": {}}
+    out = {"fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     # the commands that produced the two CSVs (their output folders are the CSVs' folders,
     # run name "t")
     fdir, wdir = os.path.dirname(fetch_csv), os.path.dirname(write_csv)
-    lines = ["# HBM traffic per launch, SF 256^3 x 360 views (rocprofv3 PMC)", "",
+    scan, _ = PROBES[probe]
+    lines = [f"# HBM traffic per launch, probe `{probe}` ({scan}; rocprofv3 PMC)", "",
              "Commands (repository root, one MI355X):", "", "```",
-             f"rocprofv3 --kernel-trace --pmc FETCH_SIZE -d {fdir} -o t --output-format csv -- python3 bench.py --traffic-probe",
-             f"rocprofv3 --kernel-trace --pmc WRITE_SIZE -d {wdir} -o t --output-format csv -- python3 bench.py --traffic-probe",
-             f"python3 bench.py --summarize-traffic {fetch_csv} {write_csv}",
+             f"rocprofv3 --kernel-trace --pmc FETCH_SIZE -d {fdir} -o t --output-format csv -- python3 bench.py --probe {probe}",
+             f"rocprofv3 --kernel-trace --pmc WRITE_SIZE -d {wdir} -o t --output-format csv -- python3 bench.py --probe {probe}",
+             f"python3 bench.py --summarize-traffic {fetch_csv} {write_csv} {probe}",
              "```", "",
              f"Calibration: a 512 MiB device copy in the same process reads FETCH_SIZE x {f_scale:.4f} and "
              f"writes WRITE_SIZE x {w_scale:.4f} of its known bytes; those factors scale every kernel below.",
-             f"Kernel source hash: `{out['source_hash']}`.", "",
+             f"Kernel source hash: `{kernel_hash()}`.", "",
              "| kernel | read MB | written MB | total MB |", "|---|---|---|---|"]
     for (nf, vf), (nw, vw) in zip(fetch, write):
         key = next((v for k, v in KERNEL_KEYS.items() if k in nf), None)
@@ -120,9 +135,152 @@ def summarize_traffic(fetch_csv, write_csv):
         rd, wr = vf * 1024 * f_scale, vw * 1024 * w_scale
         out["kernels"][key] = {"read_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr}
         lines.append(f"| {key} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {(rd + wr) / 1e6:.1f} |")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
-        json.dump(out, fh, indent=1)
-    with open(os.path.join(ROOT, "profiles", "traffic_sf_c2.md"), "w") as fh:
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            allt = json.load(fh)
+    except (OSError, ValueError):
+        allt = {}
+    if allt.get("source_hash") != kernel_hash() or "probes" not in allt:
+        allt = {"source_hash": kernel_hash(), "probes": {}}
+    allt["probes"][probe] = out
+    with open(path, "w") as fh:
+        json.dump(allt, fh, indent=1)
+    with open(os.path.join(ROOT, "profiles", f"traffic_{probe}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+# kernel-name fragments -> short names in the counter summaries
+COUNTER_KERNELS = (("fwd_kernel", "forward"), ("bwd_kernel", "backward"),
+                   ("ramp_kernel", "ramp"), ("amp_scale_kernel", "amp_scale"),
+                   ("transpose_zfast_kernel", "transpose"), ("item_max_kernel", "item_max"))
+N_CU = 256
+N_XCD = 8
+VALU_LANE_PEAK = N_CU * 128 * 2.4e9     # FP32 VALU lane-instructions/s (see VALU_PEAK)
+
+
+def summarize_counters(probe, csvs):
+    """Per-dispatch totals of rocprofv3 --pmc runs of `bench.py --probe <probe>` (several
+    passes, each its own CSV; per-SE / per-instance rows are summed), joined with the
+    dispatch durations of the same runs.  Writes profiles/counters_<probe>.md and adds the
+    figures to profiles/counters.json (keyed by the kernel source hash)."""
+    import csv
+    import collections
+    vals = collections.defaultdict(lambda: collections.defaultdict(float))
+    dur = collections.defaultdict(list)
+    names = {}
+    for path in csvs:
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        for r in csv.DictReader(open(path)):
+            key = next((v for k, v in COUNTER_KERNELS if k in r["Kernel_Name"]), None)
+            if key is None:
+                continue
+            per[r["Dispatch_Id"]][r["Counter_Name"]] += float(r["Counter_Value"])
+            names[(path, r["Dispatch_Id"])] = key
+            if "Start_Timestamp" in r and r.get("End_Timestamp"):
+                per[r["Dispatch_Id"]]["_ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        for d, cv in per.items():
+            key = names[(path, d)]
+            for c, v in cv.items():
+                if c == "_ns":
+                    dur[key].append(v)
+                else:
+                    vals[key][c] = v          # one dispatch of each kernel per probe run
+    g = {"sf_c2": "cone_c2", "dd_c2": "cone_c2", "sf_c4": "noncirc_c4"}[probe]
+    from paper_2503_16741_amd import synth
+    geom = getattr(synth, g)()
+    vv = float(geom.n_vox) * geom.n_views
+    out = {}
+    lines = [f"# Counters per dispatch, probe `{probe}` ({g}: {geom.nx}x{geom.ny}x{geom.nz}, "
+             f"{geom.n_views} views, detector {geom.nu}x{geom.nv})", "",
+             "Commands (repository root, one MI355X; one rocprofv3 run per counter group):", "", "```"]
+    for path in csvs:
+        d = os.path.dirname(path)
+        lines.append(f"rocprofv3 --kernel-trace --pmc <group> -d {d} -o t --output-format csv -- "
+                     f"python3 bench.py --probe {probe}")
+    lines += [f"python3 bench.py --summarize-counters {probe} " + " ".join(csvs), "```", "",
+              "Groups: (1) SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_LDS "
+              "SQ_LDS_BANK_CONFLICT SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE; "
+              "(2) TCC_HIT_sum TCC_MISS_sum TA_BUSY_avr SQ_INSTS_SALU SQ_WAIT_INST_ANY "
+              "SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE.", "",
+              f"Kernel source hash: `{kernel_hash()}`.  GRBM_GUI_ACTIVE is reported summed over "
+              f"the {N_XCD} XCDs, so a kernel's clock cycles are that value / {N_XCD}.  VALU issue: "
+              "a CU completes at most two wave64 FP32 VALU instructions per clock (four SIMDs, 32 "
+              "lanes each: 256 CUs x 128 lanes x 2.4 GHz = 78.6e12 lane-instructions/s, the "
+              "published 157.3 TFLOP/s counting an FMA as two), so 'VALU / CU / clk' has a ceiling "
+              "of 2.", "",
+              "| kernel | cycles (1e6) | VALU instr / voxel-view (x64 lanes) | VALU / CU / clk | "
+              "trans. instr % | SALU / VALU | LDS instr / vv | LDS bank-conflict clk / CU / clk | "
+              "VMEM rd / vv | L2 hit % | TA busy % |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for key in ("forward", "backward", "ramp", "amp_scale", "transpose", "item_max"):
+        if key not in vals:
+            continue
+        c = vals[key]
+        ms = (sorted(dur[key])[len(dur[key]) // 2] * 1e-6) if dur[key] else float("nan")
+        valu = c.get("SQ_INSTS_VALU", float("nan"))
+        cyc = c.get("GRBM_GUI_ACTIVE", float("nan")) / N_XCD
+        hit = c.get("TCC_HIT_sum", float("nan"))
+        miss = c.get("TCC_MISS_sum", float("nan"))
+        row = {"counter_run_ms": ms, "cycles": cyc, "valu_instr": valu,
+               "valu_lane_instr_per_vv": valu * 64 / vv,
+               "valu_per_cu_clk": valu / N_CU / cyc,
+               "trans_frac": c.get("SQ_INSTS_VALU_TRANS_F32", float("nan")) / valu,
+               "salu_per_valu": c.get("SQ_INSTS_SALU", float("nan")) / valu,
+               "lds_per_vv": c.get("SQ_INSTS_LDS", float("nan")) * 64 / vv,
+               "lds_conflict_per_cu_clk": c.get("SQ_LDS_BANK_CONFLICT", float("nan")) / N_CU / cyc,
+               "vmem_rd_per_vv": c.get("SQ_INSTS_VMEM_RD", float("nan")) * 64 / vv,
+               "l2_hit_pct": 100.0 * hit / (hit + miss),
+               "ta_busy_pct": 100.0 * c.get("TA_BUSY_avr", float("nan")) / cyc,
+               "raw": dict(c)}
+        out[key] = row
+        lines.append(f"| {key} | {cyc / 1e6:.2f} | {row['valu_lane_instr_per_vv']:.1f} | "
+                     f"{row['valu_per_cu_clk']:.3f} | {100 * row['trans_frac']:.1f} | "
+                     f"{row['salu_per_valu']:.2f} | {row['lds_per_vv']:.2f} | "
+                     f"{row['lds_conflict_per_cu_clk']:.3f} | {row['vmem_rd_per_vv']:.2f} | "
+                     f"{row['l2_hit_pct']:.1f} | {row['ta_busy_pct']:.1f} |")
+    lines += ["", "Per voxel-view figures are lane-level (instruction count x 64) over the scan's "
+              f"voxel-views ({vv:.4g}); for the ramp and helper kernels the same divisor only "
+              "gives a scale.  TA busy = TA_BUSY_avr over the kernel's cycles."]
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    try:
+        allc = json.load(open(path))
+    except (OSError, ValueError):
+        allc = {}
+    if allc.get("source_hash") != kernel_hash():
+        allc = {"source_hash": kernel_hash()}
+    allc[probe] = out
+    with open(path, "w") as fh:
+        json.dump(allc, fh, indent=1)
+    with open(os.path.join(ROOT, "profiles", f"counters_{probe}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_trace(stats_csv, out_name="sf_c2_kernel_stats.md"):
+    """profiles/<out_name> from the kernel statistics CSV of
+    `rocprofv3 --kernel-trace --stats -- python3 bench.py --steps 5 --warmup 1 ...`."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    d = os.path.dirname(stats_csv)
+    lines = ["# SF-TT forward + back projection, 256^3 x 360 views (kernel trace statistics)", "",
+             "Command (repository root, one MI355X):", "", "```",
+             f"rocprofv3 --kernel-trace --stats -T -d {d} -o sf_c2 --output-format csv -- "
+             "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-dd --no-recon "
+             "--no-variants --no-serving",
+             f"python3 bench.py --summarize-trace {stats_csv}", "```", "",
+             "Workload: 3D circular cone beam, 256^3 FP32 at 0.5 mm, 360 views, flat 512x384 at "
+             "0.8 mm, SAD 785, SDD 1200.  Each step: SF forward (item_max + qscale + "
+             "transpose_zfast + fwd_kernel) then SF back projection (amp_scale + bwd_kernel); "
+             "6 calls each = 1 warm-up + 5 timed steps.", f"Kernel source hash: `{kernel_hash()}`.",
+             "", "| kernel | calls | total ms | average ms | min ms | max ms | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {r['Name']} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
+                     f"{float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -175,6 +333,28 @@ def cpu_baseline(geom, vol, n_views=128, n_vox=1500000):
     return out
 
 
+def half_precision_errors(hc):
+    """CPU-baseline leg: max |gpu - oracle| / max |oracle| of half-precision results on sampled
+    views (forward) and voxels (back projection) -- on the stored (rounded) input, so that only
+    the kernel and the output rounding count, and for the forward also on the FP32 source."""
+    import numpy as np
+    import oracle
+
+    def rel(a, b):
+        return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / np.max(np.abs(b)))
+    g = hc["geom"]
+    ref = oracle.forward(g, hc["x_stored"], views=hc["views"])
+    out = {"forward_stored_input": rel(hc["y_views"], ref),
+           "back_projection": rel(hc["b_vox"], oracle.adjoint(g, hc["y_stored"],
+                                                               voxels=hc["voxels"])),
+           "sample": f"forward views {hc['views'].tolist()}, back projection at "
+                     f"{len(hc['voxels'])} random voxels"}
+    if hc["x_f32"] is not None:
+        out["forward_fp32_input"] = rel(hc["y_views"], oracle.forward(g, hc["x_f32"],
+                                                                     views=hc["views"]))
+    return {k: (round(v, 8) if isinstance(v, float) else v) for k, v in out.items()}
+
+
 def cpu_full():
     """The unmodified FP64 oracle over whole scans on all host threads: 256^3 x 360 views SF and
     DD, each direction once, and the 2D 128^2 x 180-view scan in full.  Writes
@@ -224,8 +404,8 @@ def write_cpu_full(res):
         fh.write("\n".join(lines) + "\n")
 
 
-def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, seed=0,
-                  burst=128, emit=True):
+def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, express_work=0.0,
+                  seed=0, burst=128, emit=True):
     """Serving under Poisson arrivals: requests drawn uniformly from the ladder (2D fan 256^2 and
     3D cone 128^3 / 256^3 / 384^3, 400 views) x {forward, back} x {FP32, BF16}, submitted to the
     serving engine at `load` times the rate one device sustains when the requests run one after
@@ -277,7 +457,7 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, seed
           f"alone throughput {alone_gups:.1f} GUPS", file=sys.stderr, flush=True)
 
     srv = ctproj.Server(int(arena_gb * (1 << 30)), n_slots=n_slots, max_batch=max_batch,
-                        age_cap_s=age_cap_ms * 1e-3)
+                        age_cap_s=age_cap_ms * 1e-3, express_work=express_work)
     results = []
     rng = np.random.default_rng(seed + 1)
 
@@ -311,14 +491,30 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, seed
         records = []
 
         def collect():
-            while True:
-                item = done_q.get()
-                if item is None:
-                    return
-                t, c = item
-                srv.wait(t)
-                records.append((c, srv.info(t)))
-                srv.release(t)
+            # the client consumes each result as soon as it is done, in completion order (a
+            # client that released in submission order would hold finished outputs in the
+            # arena behind a slow request, and admission would wait for that memory)
+            pending, finished = [], False
+            while not finished or pending:
+                while True:
+                    try:
+                        item = done_q.get_nowait()
+                    except queue.Empty:
+                        break
+                    if item is None:
+                        finished = True
+                    else:
+                        pending.append(item)
+                still = []
+                for t, c in pending:
+                    if srv.query(t):
+                        records.append((c, srv.info(t)))
+                        srv.release(t)
+                    else:
+                        still.append((t, c))
+                if len(still) == len(pending):
+                    time.sleep(2e-4)
+                pending = still
 
         th = threading.Thread(target=collect)
         th.start()
@@ -365,7 +561,8 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, seed
                                   "128^3 / 256^3 / 384^3 at 0.4 mm (400 views, flat 640x480 at "
                                   "0.6 mm), FP32 or BF16, 50/50 forward/back",
                       "arena_gb": arena_gb, "n_slots": n_slots, "max_batch": max_batch,
-                      "age_cap_ms": age_cap_ms, "seconds_per_load": seconds},
+                      "age_cap_ms": age_cap_ms, "express_work": express_work,
+                      "seconds_per_load": seconds},
            "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
            "alone": {"gups": round(alone_gups, 2), "mean_service_ms": round(mean_svc, 3),
                      "capacity_req_per_s": round(capacity, 2),
@@ -390,9 +587,14 @@ def main():
     ap.add_argument("--no-dd", action="store_true")
     ap.add_argument("--no-recon", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--summarize-traffic", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV [PROBE]: HBM bytes per launch into profiles/")
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the FP64 oracle over whole scans (minutes) and write its summary")
+    ap.add_argument("--summarize-counters", nargs="+", metavar=("PROBE", "CSV"),
+                    help="summarize rocprofv3 --pmc CSVs of `--probe PROBE` runs into profiles/")
+    ap.add_argument("--summarize-trace", metavar="STATS_CSV",
+                    help="write profiles/sf_c2_kernel_stats.md from a rocprofv3 kernel-stats CSV")
     ap.add_argument("--cpu-full-summarize", metavar="JSON",
                     help="write profiles/cpu_oracle_full.* from a saved --cpu-full output line")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -409,11 +611,20 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-max-batch", type=int, default=8)
     ap.add_argument("--serving-age-cap-ms", type=float, default=50.0)
+    ap.add_argument("--serving-express-work", type=float, default=1e9,
+                    help="requests of at most this many voxel-view updates (the 2D fan and 128^3 "
+                         "requests) may use the last slot, which takes nothing longer; 0: off")
     ap.add_argument("--no-serving", action="store_true",
                     help="leave the serving field out of the default run")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1:])
         return
     if args.cpu_full:
         cpu_full()
@@ -431,7 +642,7 @@ def main():
     if args.serving:
         serving_bench(args.serving_seconds, [float(v) for v in args.serving_loads.split(",")],
                       args.serving_arena_gb, args.serving_slots, args.serving_max_batch,
-                      args.serving_age_cap_ms)
+                      args.serving_age_cap_ms, args.serving_express_work)
         return
 
     import numpy as np
@@ -501,9 +712,32 @@ def main():
     vv = float(g.n_vox) * g.n_views
     value = 2.0 * vv * args.steps / wall / 1e9
     dom_name, dom_ms = ("sf_forward", fwd.mean()) if fwd.mean() >= bwd.mean() else ("sf_backward", bwd.mean())
+    dom_key = "forward" if dom_name == "sf_forward" else "backward"
     ops = SF_OPS_PER_VV * vv
-    achieved = ops / (dom_ms * 1e-3)
+    alg = ops / (dom_ms * 1e-3)
+    valu = load_counters("sf_c2", dom_key)
     traffic = load_traffic(dom_name)
+    # executed VALU lane-instructions per second over the direction's event time (which also
+    # holds its small helper kernels, so the rate is a lower bound for the kernel itself)
+    executed = None if valu is None else valu * 64 / (dom_ms * 1e-3)
+    roof = {
+        "bound": "alu",
+        "kernel": dom_name,
+        "achieved": None if executed is None else round(executed / 1e12, 3),
+        "peak": round(VALU_PEAK / 1e12, 2),
+        "unit": "T VALU lane-instructions/s (peak: 256 CUs x 128 FP32 lanes x 2.4 GHz)",
+        "frac": None if executed is None else round(executed / VALU_PEAK, 4),
+        "valu_instructions_per_launch": valu,
+        "traffic": traffic,
+        "algorithmic": {
+            "ops_per_voxel_view": round(SF_OPS_PER_VV, 2),
+            "op_unit": "FP32 operation of the SF-TT method per voxel-view (an FMA counts once)",
+            "achieved": round(alg / 1e12, 3),
+            "frac_of_valu_peak": round(alg / VALU_PEAK, 4),
+            "frac_of_fp32_157_tflops": round(2 * alg / 157.3e12, 4)},
+        "hbm_frac_algorithmic": round((vol.numel() + sino.numel()) * 4 / (dom_ms * 1e-3) / HBM_PEAK, 5),
+    }
+    half_checks = []     # half-precision results checked against the oracle in the CPU leg
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -523,18 +757,7 @@ def main():
         "p99_ms": round(float(np.percentile(pair, 99)), 4),
         "fwd_ms": round(float(fwd.mean()), 4),
         "back_ms": round(float(bwd.mean()), 4),
-        "roofline": {
-            "bound": "alu",
-            "kernel": dom_name,
-            "achieved": round(achieved / 1e12, 3),
-            "peak": round(VALU_PEAK / 1e12, 2),
-            "unit": "TFLOP/s",
-            "frac": round(achieved / VALU_PEAK, 4),
-            "ops_per_voxel_view": round(SF_OPS_PER_VV, 2),
-            "op_unit": "FP32 VALU operation (an FMA counts once); peak = 157.3 TFLOP/s / 2",
-            "traffic": traffic,
-            "hbm_frac_algorithmic": round((vol.numel() + sino.numel()) * 4 / (dom_ms * 1e-3) / HBM_PEAK, 5),
-        },
+        "roofline": roof,
     }
     plan.close()
 
@@ -552,7 +775,9 @@ def main():
         # the other scan geometries at their full sizes: curved detector (512x512x256, 720
         # views, 736x64) and non-circular poses (384^3, 500 views, 640x480, per-view jitter)
         out["variants"] = {}
-        for name, gv, method in (("curved_512x512x256_720v", synth.curved_c3(), "sf"),
+        for name, gv, method in (("fan2d_128sq_180v", synth.fan2d_c1(), "sf"),
+                                 ("fan2d_128sq_180v_dd", synth.fan2d_c1(), "dd"),
+                                 ("curved_512x512x256_720v", synth.curved_c3(), "sf"),
                                  ("noncirc_384c_500v", synth.noncirc_c4(), "sf")):
             pv = ctproj.ctp_plan_create(gv, method)
             gen = torch.Generator(device=dev)
@@ -616,26 +841,41 @@ def main():
         print(f"[bench] MBIR iteration (curved 512x512x256, 720 views): {np.mean(times[1:]):.2f} ms",
               file=sys.stderr, flush=True)
         del A, x_true, l_true, y_hat, w, x, opt
+        # the non-circular scan with half-precision storage: timing, plus sampled outputs that
+        # the CPU-baseline leg checks against the FP64 oracle (sampled views of the forward,
+        # sampled voxels of the back projection)
         g4 = synth.noncirc_c4()
         p4 = ctproj.ctp_plan_create(g4, "sf")
-        x4 = torch.rand(g4.vol_shape, generator=gen, device=dev).to(torch.bfloat16)
-        y4 = torch.empty(g4.sino_shape, dtype=torch.bfloat16, device=dev)
-        b4 = torch.empty_like(x4)
-        ctproj.ctp_project(p4, x4, y4)
-        ctproj.ctp_backproject(p4, y4, b4)
-        torch.cuda.synchronize()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        evs[0].record(stream)
-        ctproj.ctp_project(p4, x4, y4)
-        evs[1].record(stream)
-        ctproj.ctp_backproject(p4, y4, b4)
-        evs[2].record(stream)
-        torch.cuda.synchronize()
-        out["variants"]["noncirc_384c_500v_bf16"] = {
-            "method": "sf", "storage": "bf16", "fwd_ms": round(evs[0].elapsed_time(evs[1]), 3),
-            "back_ms": round(evs[1].elapsed_time(evs[2]), 3)}
+        half_views = np.array([0, 257], dtype=np.int32)
+        half_vox = np.random.default_rng(3).choice(g4.n_vox, size=300, replace=False)
+        x32 = torch.rand(g4.vol_shape, generator=gen, device=dev)
+        for dt, tag in ((torch.bfloat16, "bf16"), (torch.float16, "f16")):
+            x4 = x32.to(dt)
+            y4 = torch.empty(g4.sino_shape, dtype=dt, device=dev)
+            b4 = torch.empty_like(x4)
+            ctproj.ctp_project(p4, x4, y4)
+            ctproj.ctp_backproject(p4, y4, b4)
+            torch.cuda.synchronize()
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            evs[0].record(stream)
+            ctproj.ctp_project(p4, x4, y4)
+            evs[1].record(stream)
+            ctproj.ctp_backproject(p4, y4, b4)
+            evs[2].record(stream)
+            torch.cuda.synchronize()
+            out["variants"][f"noncirc_384c_500v_{tag}"] = {
+                "method": "sf", "storage": tag, "fwd_ms": round(evs[0].elapsed_time(evs[1]), 3),
+                "back_ms": round(evs[1].elapsed_time(evs[2]), 3)}
+            half_checks.append({
+                "key": f"noncirc_384c_500v_{tag}", "geom": g4, "views": half_views,
+                "voxels": half_vox, "x_stored": x4.float().cpu().numpy(),
+                "x_f32": x32.cpu().numpy() if tag == "bf16" else None,
+                "y_views": y4.float()[half_views.tolist()].cpu().numpy(),
+                "y_stored": y4.float().cpu().numpy(),
+                "b_vox": b4.float().reshape(-1)[torch.from_numpy(half_vox).to(dev)].cpu().numpy()})
+            del x4, y4, b4
         p4.close()
-        del x4, y4, b4
+        del x32
 
         # The paper's own DD figures (2D: 512 images of 384^2 in 1.3 s; 3D: a 384^3 volume in
         # about 2 s, RTX 4090) name no view count or detector; these are the same workloads
@@ -706,11 +946,12 @@ def main():
         del vol, sino, back
         torch.cuda.empty_cache()
         sv = serving_bench(20.0, [0.7, 0.9], args.serving_arena_gb, args.serving_slots,
-                           args.serving_max_batch, args.serving_age_cap_ms, emit=False)
+                           args.serving_max_batch, args.serving_age_cap_ms,
+                           args.serving_express_work, emit=False)
         out["serving"] = {
             "workload": sv["config"]["workload"], "seconds_per_load": 20.0,
             "n_slots": args.serving_slots, "max_batch": args.serving_max_batch,
-            "age_cap_ms": args.serving_age_cap_ms,
+            "age_cap_ms": args.serving_age_cap_ms, "express_work": args.serving_express_work,
             "serial": sv["alone"]["gups"], "mean_service_ms": sv["alone"]["mean_service_ms"],
             "burst": sv["burst"],
             "loads": [{k: r[k] for k in ("load", "n_requests", "gups", "offered_gups", "p50_ms",
@@ -720,6 +961,10 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, vol_np)
+        for hc in half_checks:
+            out["variants"][hc["key"]]["error_vs_oracle"] = half_precision_errors(hc)
+            print(f"[bench] {hc['key']}: {out['variants'][hc['key']]['error_vs_oracle']}",
+                  file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
