@@ -405,7 +405,7 @@ def write_cpu_full(res):
 
 
 def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, express_work=0.0,
-                  seed=0, burst=128, emit=True):
+                  launch_work=0.0, seed=0, burst=128, emit=True):
     """Serving under Poisson arrivals: requests drawn uniformly from the ladder (2D fan 256^2 and
     3D cone 128^3 / 256^3 / 384^3, 400 views) x {forward, back} x {FP32, BF16}, submitted to the
     serving engine at `load` times the rate one device sustains when the requests run one after
@@ -457,7 +457,8 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, expr
           f"alone throughput {alone_gups:.1f} GUPS", file=sys.stderr, flush=True)
 
     srv = ctproj.Server(int(arena_gb * (1 << 30)), n_slots=n_slots, max_batch=max_batch,
-                        age_cap_s=age_cap_ms * 1e-3, express_work=express_work)
+                        age_cap_s=age_cap_ms * 1e-3, express_work=express_work,
+                        launch_work=launch_work)
     results = []
     rng = np.random.default_rng(seed + 1)
 
@@ -562,6 +563,7 @@ def serving_bench(seconds, loads, arena_gb, n_slots, max_batch, age_cap_ms, expr
                                   "0.6 mm), FP32 or BF16, 50/50 forward/back",
                       "arena_gb": arena_gb, "n_slots": n_slots, "max_batch": max_batch,
                       "age_cap_ms": age_cap_ms, "express_work": express_work,
+                      "launch_work": launch_work,
                       "seconds_per_load": seconds},
            "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
            "alone": {"gups": round(alone_gups, 2), "mean_service_ms": round(mean_svc, 3),
@@ -613,7 +615,11 @@ def main():
     ap.add_argument("--serving-age-cap-ms", type=float, default=50.0)
     ap.add_argument("--serving-express-work", type=float, default=1e9,
                     help="requests of at most this many voxel-view updates (the 2D fan and 128^3 "
-                         "requests) may use the last slot, which takes nothing longer; 0: off")
+                         "requests) may use the last slot, which takes nothing longer, and "
+                         "longer requests run one at a time; 0: off")
+    ap.add_argument("--serving-launch-work", type=float, default=8e9,
+                    help="split each call into kernel launches of at most this many voxel-view "
+                         "updates (the 384^3 forward into three); 0: one launch per call")
     ap.add_argument("--no-serving", action="store_true",
                     help="leave the serving field out of the default run")
     args = ap.parse_args()
@@ -642,7 +648,8 @@ def main():
     if args.serving:
         serving_bench(args.serving_seconds, [float(v) for v in args.serving_loads.split(",")],
                       args.serving_arena_gb, args.serving_slots, args.serving_max_batch,
-                      args.serving_age_cap_ms, args.serving_express_work)
+                      args.serving_age_cap_ms, args.serving_express_work,
+                      args.serving_launch_work)
         return
 
     import numpy as np
@@ -947,11 +954,12 @@ def main():
         torch.cuda.empty_cache()
         sv = serving_bench(20.0, [0.7, 0.9], args.serving_arena_gb, args.serving_slots,
                            args.serving_max_batch, args.serving_age_cap_ms,
-                           args.serving_express_work, emit=False)
+                           args.serving_express_work, args.serving_launch_work, emit=False)
         out["serving"] = {
             "workload": sv["config"]["workload"], "seconds_per_load": 20.0,
             "n_slots": args.serving_slots, "max_batch": args.serving_max_batch,
             "age_cap_ms": args.serving_age_cap_ms, "express_work": args.serving_express_work,
+            "launch_work": args.serving_launch_work,
             "serial": sv["alone"]["gups"], "mean_service_ms": sv["alone"]["mean_service_ms"],
             "burst": sv["burst"],
             "loads": [{k: r[k] for k in ("load", "n_requests", "gups", "offered_gups", "p50_ms",

@@ -23,7 +23,11 @@
  *     merged call does not fit, fewer requests are merged.
  *   - Overlap.  Each slot owns a HIP stream; up to n_slots calls run concurrently.  Optionally
  *     the last slot is an express lane for short requests (express_work below): it never takes
- *     a long call, and the other slots still take short ones.
+ *     a long call, and the other slots still take short ones.  A kernel launch keeps the
+ *     compute units it holds until its work-groups drain, and while two long launches run the
+ *     units that one frees go to the other first; so with an express lane long calls run one
+ *     at a time, and launch_work splits each call into short launches between which the other
+ *     streams' kernels start.
  *
  * Results are those of ctp_project / ctp_backproject with batch = the merged count.  Every
  * batch item's result is bitwise independent of the other items of its call (the forward
@@ -57,8 +61,13 @@ typedef struct {
     double express_work;  /* with n_slots >= 2 and express_work > 0, the last slot runs only
                              calls whose requests' work (voxel-view updates) is at most this,
                              and merges at most express_work of it into one call, so short
-                             requests never wait behind a device full of long calls;
+                             requests never wait behind a device full of long calls; calls of
+                             longer requests then run one at a time;
                              0 = every slot takes every call */
+    double launch_work;   /* > 0: a call is split into kernel launches over consecutive view
+                             ranges of at most this many voxel-view updates each (at least one
+                             view), so that other slots' work starts between them; the result
+                             has the same bits.  0 = one launch per call */
 } ctp_server_config;
 
 /* Host-clock times (steady clock, ns) and placement of one request. */

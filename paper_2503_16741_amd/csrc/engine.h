@@ -83,6 +83,9 @@ struct Params {
     int64_t sino_b_stride;   // elements between batch items (3D)
     float eps;               // ramps narrower than this (cells) are steps
     int nc_runs;             // non-circular SF: column runs allowed (see the plan's bound)
+    // views [v_begin, v_begin + v_count) of a forward or back projection launch (a call may
+    // be split into several launches over consecutive view ranges); 0, n_views for a whole call
+    int v_begin, v_count;
 };
 
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.
@@ -112,9 +115,24 @@ hipError_t launch_amp_scale(const Params &p, const LaunchCfg &c, const ViewRec *
 hipError_t launch_forward(const Params &p, const LaunchCfg &c, const ViewRec *views,
                           const float *volT, const float *qscale, float *sino, int64_t batch,
                           int accumulate, hipStream_t st);
+// accumulate: 0 = vol = the gather, 1 = vol += the gather, 2 = the gather continues the sums
+// that vol holds (the view loop starts from them: a call split into launches over consecutive
+// view ranges, the later ones with 2, gives the bits of the single launch).
 hipError_t launch_backward(const Params &p, const LaunchCfg &c, const ViewRec *views,
                            const float *ysc, float *vol, int64_t batch, int accumulate,
                            hipStream_t st);
+// Forward / back projection of a call (accumulate = 0) split into launches of at most
+// views_per_launch consecutive views, with the checks and workspace of ctp_project /
+// ctp_backproject: the same bits as the single-launch call.  The serving engine uses the split
+// to bound how long one of its launches holds the device.
+ctp_status project_sliced(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
+                          ctp_dtype sino_dtype, int64_t batch, void *workspace,
+                          size_t workspace_bytes, int views_per_launch, hipStream_t stream);
+ctp_status backproject_sliced(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype,
+                              void *vol, ctp_dtype vol_dtype, int64_t batch, void *workspace,
+                              size_t workspace_bytes, int views_per_launch, hipStream_t stream);
+int plan_views(const ctp_plan *plan);
+
 // Device address of this device's copy of the library's static scratch array (looked up once
 // per device, then cached), kStaticScratchBytes long: the workspace of ctp_project_static.
 constexpr size_t kStaticScratchBytes = (size_t)96 << 20;

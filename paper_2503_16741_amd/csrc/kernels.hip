@@ -1162,9 +1162,9 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4))
     // overlap) and every XCD gets a mix of central and edge strips.
     const int n_strips = (P.nu + kStripW - 1) / kStripW;
     const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
-    if (kk >= ((n_strips - xcd + 7) >> 3) * P.n_views)
+    if (kk >= ((n_strips - xcd + 7) >> 3) * P.v_count)
         return;
-    const int strip = xcd + 8 * (kk / P.n_views), view = kk % P.n_views;
+    const int strip = xcd + 8 * (kk / P.v_count), view = P.v_begin + kk % P.v_count;
     const int chunk = blockIdx.y % n_row_chunks;
     const int b = blockIdx.y / n_row_chunks;            // batch item (3D); 0 in 2D
     const int i_lo = strip * kStripW;
@@ -2146,9 +2146,18 @@ __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_ker
 #pragma unroll
     for (int q = 0; q < kZChunk; ++q)
         acc[q] = 0.0f;
+    if (accumulate == 2 && valid) {
+        // a later launch of a view-split call: continue the sums of the earlier views
+        const float *vs = vol + (GEOM == kFan2D ? 0 : (int64_t)b * P.vol_b_stride) +
+                          (int64_t)iy * P.nx + ix;
+#pragma unroll
+        for (int q = 0; q < kZChunk; ++q)
+            if (zc0 + q < nzv)
+                acc[q] = vs[(int64_t)(zc0 + q) * P.vol_z_stride];
+    }
 
     if (valid) {
-        for (int view = 0; view < P.n_views; ++view) {
+        for (int view = P.v_begin; view < P.v_begin + P.v_count; ++view) {
             const ViewRec &V = views[view];
             const float *yv = ysb + (int64_t)view * P.sino_view_stride;
             const float zb0 = P.z0 - hz - V.s[2];
@@ -2269,7 +2278,7 @@ __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_ker
             const int z = zc0 + q;
             if (z < nzv) {
                 float *dst = vb + (int64_t)z * P.vol_z_stride;
-                *dst = accumulate ? *dst + acc[q] : acc[q];
+                *dst = accumulate == 1 ? *dst + acc[q] : acc[q];
             }
         }
     }
@@ -2400,7 +2409,7 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
     const int R = min(kRowsMax, rows_total);
     size_t lds = ((size_t)(R + 1) * fwd_row_width<GEOM, METHOD, K>() + kMaxCells) * sizeof(int);
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
-    dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.n_views),
+    dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.v_count),
               (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
     hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(kFwdThreads), lds, st, p, views,
                        volT, qscale, sino, accumulate, nchunks);

@@ -121,6 +121,7 @@ double plan_work(const ctp_plan *plan)
     const ctp_geometry_desc &g = plan->g;
     return (double)g.nx * g.ny * (g.kind == CTP_FAN2D ? 1 : g.nz) * g.n_views;
 }
+int plan_views(const ctp_plan *plan) { return plan->g.n_views; }
 }  // namespace ctp
 
 extern "C" {
@@ -381,6 +382,8 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     p.du = (float)g.du;
     p.dv = (float)(two_d ? 1.0 : g.dv);
     p.n_views = g.n_views;
+    p.v_begin = 0;
+    p.v_count = g.n_views;
     p.eps = 1e-6f;
     // non-circular SF column runs: expansion accurate to 2e-5 cells / rows, a run's footprints
     // within K + 1 cells (their union is narrower than K: widths below K - 1 plus the drift)
@@ -569,7 +572,7 @@ namespace {
 // The forward projection into a validated workspace (prepare_call has run).
 ctp_status project_into(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
                         ctp_dtype sino_dtype, int64_t batch, int accumulate, void *workspace,
-                        const ctp::Params &p, hipStream_t stream)
+                        ctp::Params p, hipStream_t stream, int views_per_launch = 0)
 {
     const FwdWs w = fwd_ws_layout(plan, batch, sino_dtype);
     char *ws = static_cast<char *>(workspace);
@@ -584,9 +587,16 @@ ctp_status project_into(const ctp_plan *plan, const void *vol, ctp_dtype vol_dty
     if (e == hipSuccess)
         e = ctp::launch_transpose_zfast(vol, (int)vol_dtype, volT, qscale, w.tr_batch, w.tr_nz,
                                         w.plane, plan->g.kind == CTP_FAN2D ? 1 : 0, stream);
-    if (e == hipSuccess)
+    // each view's cells are written by its own work-groups, so launches over consecutive view
+    // ranges give the bits of one launch over all views
+    const int nv = plan->g.n_views;
+    const int step = views_per_launch > 0 ? std::min(views_per_launch, nv) : nv;
+    for (int v0 = 0; v0 < nv && e == hipSuccess; v0 += step) {
+        p.v_begin = v0;
+        p.v_count = std::min(step, nv - v0);
         e = ctp::launch_forward(p, plan->cfg, plan->d_views, volT, qscale, out, batch,
                                 half_out ? 0 : accumulate, stream);
+    }
     if (e == hipSuccess && half_out) {
         size_t sb = 0;
         ctp_plan_bytes(plan, CTP_F32, batch, nullptr, &sb);
@@ -609,8 +619,8 @@ ctp_status ctp_project(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtyp
                                  workspace_bytes, CTP_FORWARD, p);
     if (st != CTP_OK)
         return st;
-    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, accumulate, workspace, p,
-                        stream);
+    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, accumulate ? 1 : 0,
+                        workspace, p, stream);
 }
 
 ctp_status ctp_project_static(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype,
@@ -637,20 +647,22 @@ ctp_status ctp_project_static(const ctp_plan *plan, const void *vol, ctp_dtype v
                       ctp::kStaticScratchBytes, CTP_FORWARD, p);
     if (st != CTP_OK)
         return st;
-    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, accumulate, scratch, p,
-                        stream);
+    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, accumulate ? 1 : 0,
+                        scratch, p, stream);
 }
 
-ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *vol,
-                           ctp_dtype vol_dtype, int64_t batch, int accumulate, void *workspace,
-                           size_t workspace_bytes, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// The back projection into a validated workspace (prepare_call has run), in launches of at most
+// views_per_launch views (0: one launch): the first launch starts each voxel's sum, the later
+// ones continue it, so every voxel adds its views in the same order as in a single launch.
+ctp_status backproject_into(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype,
+                            void *vol, ctp_dtype vol_dtype, int64_t batch, int accumulate,
+                            void *workspace, ctp::Params p, hipStream_t stream,
+                            int views_per_launch = 0)
 {
-    g_last_error.clear();
-    ctp::Params p;
-    ctp_status st = prepare_call(plan, sino, vol, sino_dtype, vol_dtype, batch, workspace,
-                                 workspace_bytes, CTP_BACKWARD, p);
-    if (st != CTP_OK)
-        return st;
     const BwdWs w = bwd_ws_layout(plan, batch, vol_dtype, sino_dtype);
     char *ws = static_cast<char *>(workspace);
     const float *ys = static_cast<const float *>(sino);
@@ -662,9 +674,16 @@ ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sin
     }
     const bool half_out = vol_dtype != CTP_F32;
     float *out = half_out ? reinterpret_cast<float *>(ws + w.vol_off) : static_cast<float *>(vol);
-    if (e == hipSuccess)
+    const int nv = plan->g.n_views;
+    const int step = views_per_launch > 0 ? std::min(views_per_launch, nv) : nv;
+    if (step < nv && accumulate && !half_out)
+        return fail(CTP_EINVAL, "a back projection split over launches cannot accumulate");
+    for (int v0 = 0; v0 < nv && e == hipSuccess; v0 += step) {
+        p.v_begin = v0;
+        p.v_count = std::min(step, nv - v0);
         e = ctp::launch_backward(p, plan->cfg, plan->d_views, ys, out, batch,
-                                 half_out ? 0 : accumulate, stream);
+                                 v0 > 0 ? 2 : half_out ? 0 : accumulate, stream);
+    }
     if (e == hipSuccess && half_out) {
         size_t vb = 0;
         ctp_plan_bytes(plan, CTP_F32, batch, &vb, nullptr);
@@ -672,6 +691,64 @@ ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sin
     }
     return finish(e, stream, "back projection");
 }
+
+}  // namespace
+
+extern "C" {
+
+ctp_status ctp_backproject(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *vol,
+                           ctp_dtype vol_dtype, int64_t batch, int accumulate, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    ctp::Params p;
+    ctp_status st = prepare_call(plan, sino, vol, sino_dtype, vol_dtype, batch, workspace,
+                                 workspace_bytes, CTP_BACKWARD, p);
+    if (st != CTP_OK)
+        return st;
+    return backproject_into(plan, sino, sino_dtype, vol, vol_dtype, batch, accumulate ? 1 : 0,
+                            workspace, p, stream);
+}
+
+}  // extern "C"
+
+namespace ctp {
+
+ctp_status project_sliced(const ctp_plan *plan, const void *vol, ctp_dtype vol_dtype, void *sino,
+                          ctp_dtype sino_dtype, int64_t batch, void *workspace,
+                          size_t workspace_bytes, int views_per_launch, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (views_per_launch < 1)
+        return fail(CTP_EINVAL, "views_per_launch must be >= 1");
+    Params p;
+    ctp_status st = prepare_call(plan, vol, sino, vol_dtype, sino_dtype, batch, workspace,
+                                 workspace_bytes, CTP_FORWARD, p);
+    if (st != CTP_OK)
+        return st;
+    return project_into(plan, vol, vol_dtype, sino, sino_dtype, batch, 0, workspace, p, stream,
+                        views_per_launch);
+}
+
+ctp_status backproject_sliced(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype,
+                              void *vol, ctp_dtype vol_dtype, int64_t batch, void *workspace,
+                              size_t workspace_bytes, int views_per_launch, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (views_per_launch < 1)
+        return fail(CTP_EINVAL, "views_per_launch must be >= 1");
+    Params p;
+    ctp_status st = prepare_call(plan, sino, vol, sino_dtype, vol_dtype, batch, workspace,
+                                 workspace_bytes, CTP_BACKWARD, p);
+    if (st != CTP_OK)
+        return st;
+    return backproject_into(plan, sino, sino_dtype, vol, vol_dtype, batch, 0, workspace, p,
+                            stream, views_per_launch);
+}
+
+}  // namespace ctp
+
+extern "C" {
 
 ctp_status ctp_ramp_filter(const ctp_plan *plan, const void *sino, ctp_dtype sino_dtype, void *out,
                            ctp_dtype out_dtype, int64_t batch, ctp_window window,

@@ -8,7 +8,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <deque>
 #include <memory>
@@ -88,7 +90,9 @@ struct ctp_server {
     char *arena = nullptr;
     int max_batch = 1;
     int64_t age_cap_ns = 0;             // 0: strict first come, first served
-    double express_work = 0.0;          // > 0: the last slot takes only calls this short
+    double express_work = 0.0;          // > 0: the last slot takes only calls this short, and
+                                        // longer calls run one at a time
+    double launch_work = 0.0;           // > 0: most voxel-view updates per kernel launch
     std::vector<Slot> slots;
 
     std::mutex mu;
@@ -115,6 +119,14 @@ struct ctp_server {
     bool is_express(int slot) const
     {
         return express_work > 0.0 && slots.size() >= 2 && slot == (int)slots.size() - 1;
+    }
+    bool is_long(const Request *r) const { return express_work > 0.0 && r->work > express_work; }
+    bool long_running() const
+    {
+        for (const Slot &s : slots)
+            if (s.batch && is_long(s.batch->items.front()))
+                return true;
+        return false;
     }
     void free_batch_scratch(Batch &b)
     {
@@ -190,7 +202,10 @@ struct ctp_server {
     // kept for it), so no request waits behind later ones for longer than the cap.  Returns an
     // empty pointer if nothing may start now.
     // The express slot considers only short requests, and an aged long request does not hold
-    // it (it can never run there).
+    // it (it can never run there).  Long requests run one at a time (each fills the device on
+    // its own, and while two run the hardware hands the compute units freed by one to the
+    // other before a third stream's work); one that waits for the running long call does not
+    // hold the other slots either.
     std::shared_ptr<Batch> admit(int slot)
     {
         size_t n_aged = 0;
@@ -198,8 +213,11 @@ struct ctp_server {
             queue, now_ns(), age_cap_ns,
             [](const Request *r) { return std::make_pair(r->work, r->t_submit); }, &n_aged);
         const bool express = is_express(slot);
+        const bool long_busy = long_running();
         for (size_t k = 0; k < order.size(); ++k) {
             if (express && queue[order[k]]->work > express_work)
+                continue;
+            if (long_busy && is_long(queue[order[k]]))
                 continue;
             std::shared_ptr<Batch> b = try_admit(order[k], slot);
             if (b || k < n_aged)
@@ -296,12 +314,20 @@ struct ctp_server {
         }
         void *ws = b.ws_bytes > 0 ? scratch + b.staging : nullptr;
         void *out = arena + b.out_off;
+        // split the call over view ranges so that no launch holds the device much longer than
+        // launch_work updates take (the other slots' work starts between launches)
+        const int nv = ctp::plan_views(head->plan);
+        int vpl = nv;
+        if (launch_work > 0.0 && head->work > 0.0) {
+            const double per_view = head->work * (double)n / (double)nv;
+            vpl = (int)std::max(1.0, std::min((double)nv, std::floor(launch_work / per_view)));
+        }
         const ctp_status st =
             head->dir == CTP_FORWARD
-                ? ctp_project(head->plan, in, head->in_dt, out, head->out_dt, n, 0, ws, b.ws_bytes,
-                              s.stream)
-                : ctp_backproject(head->plan, in, head->in_dt, out, head->out_dt, n, 0, ws,
-                                  b.ws_bytes, s.stream);
+                ? ctp::project_sliced(head->plan, in, head->in_dt, out, head->out_dt, n, ws,
+                                      b.ws_bytes, vpl, s.stream)
+                : ctp::backproject_sliced(head->plan, in, head->in_dt, out, head->out_dt, n, ws,
+                                          b.ws_bytes, vpl, s.stream);
         if (st != CTP_OK) {
             msg = ctp_last_error();
             return false;
@@ -422,6 +448,8 @@ ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out)
         return ctp::set_error(CTP_EINVAL, "age_cap_us must be >= 0");
     if (!(cfg->express_work >= 0.0))
         return ctp::set_error(CTP_EINVAL, "express_work must be >= 0");
+    if (!(cfg->launch_work >= 0.0))
+        return ctp::set_error(CTP_EINVAL, "launch_work must be >= 0");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess)
         return ctp::set_error(CTP_EDEVICE, "no HIP device");
@@ -433,6 +461,7 @@ ctp_status ctp_server_create(const ctp_server_config *cfg, ctp_server **out)
     s->max_batch = cfg->max_batch;
     s->age_cap_ns = cfg->age_cap_us * 1000;
     s->express_work = cfg->express_work;
+    s->launch_work = cfg->launch_work;
     s->alloc.reset(cfg->arena_bytes);
     s->slots.resize((size_t)cfg->n_slots);
     for (Slot &sl : s->slots) {

@@ -66,7 +66,8 @@ class _Desc(ctypes.Structure):
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("age_cap_us", ctypes.c_int64), ("express_work", ctypes.c_double)]
+                ("age_cap_us", ctypes.c_int64), ("express_work", ctypes.c_double),
+                ("launch_work", ctypes.c_double)]
 
 
 class _RequestInfo(ctypes.Structure):
@@ -404,17 +405,19 @@ class Server:
     admission needs one contiguous block per call.  Requests that have waited ``age_cap_s`` are
     served in arrival order; younger ones smallest first (``age_cap_s=0``: strict arrival
     order).  With ``express_work`` > 0 the last slot runs only requests of at most that many
-    voxel-view updates.
+    voxel-view updates, and longer requests run one at a time.  With ``launch_work`` > 0 each
+    call is split into kernel launches of at most that many voxel-view updates (same results).
     """
 
     def __init__(self, arena_bytes: int, n_slots: int = 4, max_batch: int = 16, device=None,
-                 age_cap_s: float = 0.05, express_work: float = 0.0):
+                 age_cap_s: float = 0.05, express_work: float = 0.0, launch_work: float = 0.0):
         import torch
         self.device = torch.device(device or "cuda")
         # uint8 arena; torch's allocations are at least 256-byte aligned
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         cfg = _ServerConfig(self.arena.data_ptr(), int(arena_bytes), int(n_slots), int(max_batch),
-                            int(round(age_cap_s * 1e6)), float(express_work))
+                            int(round(age_cap_s * 1e6)), float(express_work),
+                            float(launch_work))
         out = ctypes.c_void_p()
         _check(lib().ctp_server_create(ctypes.byref(cfg), ctypes.byref(out)), "ctp_server_create")
         self.handle = out

@@ -8,7 +8,8 @@
 // Failure handling: calls that fail to launch and calls whose completion reports a device error
 // (injected through plans marked to fail) fail their own requests only, while every other
 // request in flight completes and all arena memory comes back; queued requests can be
-// cancelled; small requests overtake a long queue of large ones until the age cap.
+// cancelled; small requests overtake a long queue of large ones until the age cap; with an
+// express threshold long calls run one at a time, split into launches by launch_work.
 // Prints "ok" and exits 0 on success.
 #include "../../paper_2503_16741_amd/csrc/server.cpp"
 
@@ -101,6 +102,7 @@ struct ctp_plan {
     bool two_d = false, recon = false, sf = true;
     size_t nvox = 0, ncell = 0, plane = 0;
     double us_per_item = 10.0;
+    int n_views = 8;
     int fail = 0;                // 1: the call fails to launch; 2: it fails on the device
 };
 
@@ -113,6 +115,7 @@ ctp_status set_error(ctp_status st, const std::string &msg) { sim_err = msg; ret
 void clear_error() { sim_err.clear(); }
 int plan_device(const ctp_plan *plan) { return plan->device; }
 double plan_work(const ctp_plan *plan) { return plan->us_per_item; }
+int plan_views(const ctp_plan *plan) { return plan->n_views; }
 }  // namespace ctp
 extern "C" const char *ctp_last_error(void) { return sim_err.c_str(); }
 
@@ -146,9 +149,11 @@ extern "C" ctp_status ctp_workspace_bytes(const ctp_plan *p, ctp_direction dir, 
 }
 
 static std::atomic<int> bad_calls{0};
+static std::atomic<int> launches{0};    // kernel launches of the projector calls
 
+// One call: its work enqueued on the stream as ceil(n_views / views_per_launch) launches.
 static ctp_status sim_call(const ctp_plan *p, ctp_direction dir, ctp_dtype vd, ctp_dtype sd,
-                           int64_t batch, void *ws, size_t ws_bytes, hipStream_t st)
+                           int64_t batch, void *ws, size_t ws_bytes, int vpl, hipStream_t st)
 {
     size_t need = 0;
     ctp_workspace_bytes(p, dir, vd, sd, batch, &need);
@@ -156,9 +161,17 @@ static ctp_status sim_call(const ctp_plan *p, ctp_direction dir, ctp_dtype vd, c
         ++bad_calls;
         return ctp::set_error(CTP_EINVAL, "workspace too small or misaligned");
     }
+    if (vpl < 1) {
+        ++bad_calls;
+        return ctp::set_error(CTP_EINVAL, "views_per_launch must be >= 1");
+    }
     if (p->fail == 1)
         return ctp::set_error(CTP_EDEVICE, "injected launch failure");
-    enqueue(st, p->us_per_item * (double)batch);
+    for (int v0 = 0; v0 < p->n_views; v0 += vpl) {
+        const int n = std::min(vpl, p->n_views - v0);
+        enqueue(st, p->us_per_item * (double)batch * n / p->n_views);
+        ++launches;
+    }
     if (p->fail == 2) {
         std::lock_guard<std::mutex> lk(st->mu);
         st->poisoned = true;
@@ -166,17 +179,19 @@ static ctp_status sim_call(const ctp_plan *p, ctp_direction dir, ctp_dtype vd, c
     return CTP_OK;
 }
 
-extern "C" ctp_status ctp_project(const ctp_plan *p, const void *, ctp_dtype vd, void *, ctp_dtype sd,
-                                  int64_t batch, int, void *ws, size_t wsb, hipStream_t st)
+namespace ctp {
+ctp_status project_sliced(const ctp_plan *p, const void *, ctp_dtype vd, void *, ctp_dtype sd,
+                          int64_t batch, void *ws, size_t wsb, int vpl, hipStream_t st)
 {
-    return sim_call(p, CTP_FORWARD, vd, sd, batch, ws, wsb, st);
+    return sim_call(p, CTP_FORWARD, vd, sd, batch, ws, wsb, vpl, st);
 }
 
-extern "C" ctp_status ctp_backproject(const ctp_plan *p, const void *, ctp_dtype sd, void *, ctp_dtype vd,
-                                      int64_t batch, int, void *ws, size_t wsb, hipStream_t st)
+ctp_status backproject_sliced(const ctp_plan *p, const void *, ctp_dtype sd, void *, ctp_dtype vd,
+                              int64_t batch, void *ws, size_t wsb, int vpl, hipStream_t st)
 {
-    return sim_call(p, CTP_BACKWARD, vd, sd, batch, ws, wsb, st);
+    return sim_call(p, CTP_BACKWARD, vd, sd, batch, ws, wsb, vpl, st);
 }
+}  // namespace ctp
 
 #define CHECK(c)                                                                          \
     do {                                                                                  \
@@ -219,8 +234,9 @@ static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, i
     // odd seeds: strict arrival order; even: age cap 20 ms; every third seed with two or more
     // slots also reserves the last slot for the small plans
     const double express = (seed % 3 == 0 && slots >= 2) ? 100.0 : 0.0;   // plan_work: us per item
+    // every fourth seed splits calls into launches of at most 150 us of work
     ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch,
-                          seed % 2 ? 0 : 20000, express};
+                          seed % 2 ? 0 : 20000, express, seed % 4 == 0 ? 150.0 : 0.0};
     ctp_server *srv = nullptr;
     CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
     static char dummy_input[16];
@@ -258,10 +274,10 @@ static void burst(unsigned seed, size_t arena_bytes, int slots, int max_batch, i
 }
 
 static ctp_server *make_server(size_t arena_bytes, int slots, int max_batch, int64_t age_cap_us,
-                               double express_work = 0.0)
+                               double express_work = 0.0, double launch_work = 0.0)
 {
     ctp_server_config cfg{reinterpret_cast<void *>((uintptr_t)1 << 40), arena_bytes, slots, max_batch,
-                          age_cap_us, express_work};
+                          age_cap_us, express_work, launch_work};
     ctp_server *srv = nullptr;
     CHECK(ctp_server_create(&cfg, &srv) == CTP_OK);
     return srv;
@@ -467,6 +483,55 @@ static void express_slot()
     CHECK(ctp_server_destroy(srv) == CTP_OK);
 }
 
+// With an express threshold, long calls run one at a time on the regular slots while short
+// ones run beside them; launch_work splits each long call into launches of a quarter of it.
+static void long_calls_one_at_a_time()
+{
+    ctp_plan big, small;
+    big.nvox = 32 * 32 * 32; big.ncell = 20 * 40 * 40; big.us_per_item = 8000;
+    small.nvox = 8 * 8 * 8; small.ncell = 4 * 10 * 10; small.us_per_item = 300;
+    static char dummy_input[16];
+    const double big_work = ctp::plan_work(&big);
+    ctp_server *srv = make_server(256u << 20, 4, 1, 0, ctp::plan_work(&small), big_work / 4);
+    const int launches0 = launches;
+    std::vector<uint64_t> bigs, smalls;
+    for (int i = 0; i < 4; ++i) {
+        uint64_t t = 0;
+        CHECK(ctp_server_submit(srv, &big, CTP_FORWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+        bigs.push_back(t);
+    }
+    wait_running(srv, bigs[0]);
+    for (int i = 0; i < 6; ++i) {
+        uint64_t t = 0;
+        CHECK(ctp_server_submit(srv, &small, CTP_BACKWARD, dummy_input, CTP_F32, CTP_F32, nullptr, &t) == CTP_OK);
+        smalls.push_back(t);
+    }
+    for (uint64_t t : bigs)
+        CHECK(ctp_server_wait(srv, t, 20 * 1000 * 1000, nullptr) == CTP_OK);
+    for (uint64_t t : smalls)
+        CHECK(ctp_server_wait(srv, t, 20 * 1000 * 1000, nullptr) == CTP_OK);
+    std::vector<ctp_request_info> bi(bigs.size());
+    for (size_t i = 0; i < bigs.size(); ++i)
+        CHECK(ctp_server_info(srv, bigs[i], &bi[i]) == CTP_OK);
+    for (size_t i = 0; i < bi.size(); ++i)
+        for (size_t j = i + 1; j < bi.size(); ++j)     // no two long calls overlap
+            CHECK(bi[i].done_ns <= bi[j].admit_ns || bi[j].done_ns <= bi[i].admit_ns);
+    int64_t last_admit = 0;
+    for (const ctp_request_info &b : bi)
+        last_admit = std::max(last_admit, b.admit_ns);
+    for (uint64_t t : smalls) {
+        ctp_request_info si{};
+        CHECK(ctp_server_info(srv, t, &si) == CTP_OK);
+        CHECK(si.done_ns < last_admit);                 // the short ones ran beside the long ones
+    }
+    // each long call in 4 launches (8 views, 2 per launch), each short one in 1
+    CHECK(launches - launches0 == 4 * 4 + 6);
+    std::vector<uint64_t> all(bigs);
+    all.insert(all.end(), smalls.begin(), smalls.end());
+    release_all_and_drain(srv, all);
+    CHECK(ctp_server_destroy(srv) == CTP_OK);
+}
+
 int main()
 {
     // the configuration of the GPU serving test, then tighter arenas and other slot counts
@@ -483,6 +548,7 @@ int main()
     cancellation();
     ordering();
     express_slot();
+    long_calls_one_at_a_time();
     std::printf("ok\n");
     return 0;
 }

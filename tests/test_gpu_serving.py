@@ -60,10 +60,13 @@ def make_input(torch, geom, direction, dtype, seed):
     return torch.from_numpy(a).cuda().to(dtype).contiguous()
 
 
-@pytest.mark.parametrize("n_slots,express", [(2, False), (3, True)])
-def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc, n_slots, express):
+@pytest.mark.parametrize("n_slots,express,sliced", [(2, False, False), (3, True, False),
+                                                    (4, True, True)])
+def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc, n_slots, express, sliced):
     """Every result of a mixed burst equals the direct batch-1 call bit for bit; with an
-    express slot (the last one, for the small kinds only) the long calls never run there."""
+    express slot (the last one, for the small kinds only) the long calls never run there and
+    run one at a time.  Sliced: every call is split into launches of a few views (the long
+    ones into one launch per view), with the same bits."""
     torch = torch_gpu
     from paper_2503_16741_amd import ctproj
     geo = geometries()
@@ -72,7 +75,8 @@ def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc, n_slots, express):
     small_work = max(w for k, w in work.items() if k != "big")
     assert small_work < work["big"]
     srv = ctproj.Server(256 << 20, n_slots=n_slots, max_batch=6,
-                        express_work=small_work if express else 0.0)
+                        express_work=small_work if express else 0.0,
+                        launch_work=small_work / 5 if sliced else 0.0)
     rng = np.random.default_rng(42)
     reqs = []
     # four long calls first (two run, two wait), so that the burst behind them queues and
@@ -110,6 +114,9 @@ def test_mixed_burst_alone_equals_in_mix(torch_gpu, orc, n_slots, express):
     if express:
         assert all(i["slot"] != n_slots - 1 for r, i in zip(reqs, infos) if r[0] == "big")
         assert any(i["slot"] == n_slots - 1 for i in infos)
+        # one interval per call (merged requests share theirs)
+        big = sorted({(i["admit_ns"], i["done_ns"]) for r, i in zip(reqs, infos) if r[0] == "big"})
+        assert all(a[1] <= b[0] for a, b in zip(big, big[1:])), "long calls overlapped"
     # bitwise: alone (batch 1, direct call) == in the mix
     for (k, d, dt, odt, seed), x, y in zip(reqs, inputs, served):
         ref = alone(ctproj, plans[k], d, x, odt)

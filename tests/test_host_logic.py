@@ -57,7 +57,7 @@ int main(void) {
     P(ctp_geometry_desc, v_ofst); P(ctp_geometry_desc, len_theta); P(ctp_geometry_desc, len_v_ofst);
     S(ctp_server_config); P(ctp_server_config, arena_bytes); P(ctp_server_config, n_slots);
     P(ctp_server_config, max_batch); P(ctp_server_config, age_cap_us);
-    P(ctp_server_config, express_work);
+    P(ctp_server_config, express_work); P(ctp_server_config, launch_work);
     S(ctp_request_info); P(ctp_request_info, done_ns); P(ctp_request_info, batch);
     P(ctp_request_info, slot);
     S(ctp_server_stats); P(ctp_server_stats, calls); P(ctp_server_stats, cancelled);
