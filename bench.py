@@ -49,6 +49,11 @@ WORKLOAD = ("3D circular cone-beam SF-TT forward+back: 256^3 FP32 at 0.5 mm (20 
 PROBES = {"sf_c2": ("cone_c2", "sf"), "dd_c2": ("cone_c2", "dd"), "sf_c4": ("noncirc_c4", "sf")}
 
 
+def synth_module():
+    from paper_2503_16741_amd import synth
+    return synth
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "plan.cpp", "engine.h"):
@@ -258,24 +263,40 @@ def summarize_counters(probe, csvs):
     print("\n".join(lines))
 
 
-def summarize_trace(stats_csv, out_name="sf_c2_kernel_stats.md"):
-    """profiles/<out_name> from the kernel statistics CSV of
-    `rocprofv3 --kernel-trace --stats -- python3 bench.py --steps 5 --warmup 1 ...`."""
+def summarize_trace(stats_csv, probe=None):
+    """profiles/sf_c2_kernel_stats.md from the kernel statistics CSV of
+    `rocprofv3 --kernel-trace --stats -- python3 bench.py --steps 5 --warmup 1 ...`, or, with a
+    probe name, profiles/<probe>_kernel_stats.md from one of `bench.py --probe <probe>`."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     d = os.path.dirname(stats_csv)
-    lines = ["# SF-TT forward + back projection, 256^3 x 360 views (kernel trace statistics)", "",
-             "Command (repository root, one MI355X):", "", "```",
-             f"rocprofv3 --kernel-trace --stats -T -d {d} -o sf_c2 --output-format csv -- "
-             "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-dd --no-recon "
-             "--no-variants --no-serving",
-             f"python3 bench.py --summarize-trace {stats_csv}", "```", "",
-             "Workload: 3D circular cone beam, 256^3 FP32 at 0.5 mm, 360 views, flat 512x384 at "
-             "0.8 mm, SAD 785, SDD 1200.  Each step: SF forward (item_max + qscale + "
-             "transpose_zfast + fwd_kernel) then SF back projection (amp_scale + bwd_kernel); "
-             "6 calls each = 1 warm-up + 5 timed steps.", f"Kernel source hash: `{kernel_hash()}`.",
-             "", "| kernel | calls | total ms | average ms | min ms | max ms | % |",
-             "|---|---|---|---|---|---|---|"]
+    if probe is None:
+        out_name = "sf_c2_kernel_stats.md"
+        lines = ["# SF-TT forward + back projection, 256^3 x 360 views (kernel trace statistics)",
+                 "", "Command (repository root, one MI355X):", "", "```",
+                 f"rocprofv3 --kernel-trace --stats -T -d {d} -o sf_c2 --output-format csv -- "
+                 "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-dd --no-recon "
+                 "--no-variants --no-serving",
+                 f"python3 bench.py --summarize-trace {stats_csv}", "```", "",
+                 "Workload: 3D circular cone beam, 256^3 FP32 at 0.5 mm, 360 views, flat 512x384 "
+                 "at 0.8 mm, SAD 785, SDD 1200.  Each step: SF forward (item_max + qscale + "
+                 "transpose_zfast + fwd_kernel) then SF back projection (amp_scale + "
+                 "bwd_kernel); 6 calls each = 1 warm-up + 5 timed steps."]
+    else:
+        scan, method = PROBES[probe]
+        out_name = f"{probe}_kernel_stats.md"
+        g = getattr(synth_module(), scan)()
+        lines = [f"# {method.upper()} forward + back projection, probe `{probe}` ({scan}: "
+                 f"{g.nx}x{g.ny}x{g.nz}, {g.n_views} views, detector {g.nu}x{g.nv}; kernel "
+                 "trace statistics)", "", "Command (repository root, one MI355X):", "", "```",
+                 f"rocprofv3 --kernel-trace --stats -T -d {d} -o {probe} --output-format csv -- "
+                 f"python3 bench.py --probe {probe}",
+                 f"python3 bench.py --summarize-trace {stats_csv} {probe}", "```", "",
+                 "One forward and one back projection (plus a 512 MiB device copy that calibrates "
+                 "the traffic counters)."]
+    lines += [f"Kernel source hash: `{kernel_hash()}`.",
+              "", "| kernel | calls | total ms | average ms | min ms | max ms | % |",
+              "|---|---|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| {r['Name']} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
@@ -595,8 +616,9 @@ def main():
                     help="time the FP64 oracle over whole scans (minutes) and write its summary")
     ap.add_argument("--summarize-counters", nargs="+", metavar=("PROBE", "CSV"),
                     help="summarize rocprofv3 --pmc CSVs of `--probe PROBE` runs into profiles/")
-    ap.add_argument("--summarize-trace", metavar="STATS_CSV",
-                    help="write profiles/sf_c2_kernel_stats.md from a rocprofv3 kernel-stats CSV")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="STATS_CSV",
+                    help="STATS_CSV [PROBE]: write profiles/sf_c2_kernel_stats.md (or "
+                         "profiles/PROBE_kernel_stats.md) from a rocprofv3 kernel-stats CSV")
     ap.add_argument("--cpu-full-summarize", metavar="JSON",
                     help="write profiles/cpu_oracle_full.* from a saved --cpu-full output line")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -617,9 +639,10 @@ def main():
                     help="requests of at most this many voxel-view updates (the 2D fan and 128^3 "
                          "requests) may use the last slot, which takes nothing longer, and "
                          "longer requests run one at a time; 0: off")
-    ap.add_argument("--serving-launch-work", type=float, default=8e9,
+    ap.add_argument("--serving-launch-work", type=float, default=0.0,
                     help="split each call into kernel launches of at most this many voxel-view "
-                         "updates (the 384^3 forward into three); 0: one launch per call")
+                         "updates (8e9: the 384^3 forward into three; halves the short requests' "
+                         "p99, costs ~7 %% of saturated throughput); 0: one launch per call")
     ap.add_argument("--no-serving", action="store_true",
                     help="leave the serving field out of the default run")
     args = ap.parse_args()
@@ -627,7 +650,7 @@ def main():
         summarize_traffic(*args.summarize_traffic)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace)
+        summarize_trace(*args.summarize_trace)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1:])

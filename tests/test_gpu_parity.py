@@ -357,7 +357,7 @@ def test_benchmark_scan_parity(torch_gpu, orc, name, method, views):
     assert np.all(np.isfinite(y))
     sel = np.arange(g.n_views) if views is None else np.asarray(views)
     ref = orc.forward(g, vol, method=method, views=sel)
-    assert rel_err(y[sel], ref) <= TOL
+    e_f = rel_err(y[sel], ref)
     # adjoint of a seeded sinogram, sampled voxels
     ys = synth.random_sinogram(g, seed=1)
     xb = run_bwd(torch_gpu, plan, ys)
@@ -366,5 +366,9 @@ def test_benchmark_scan_parity(torch_gpu, orc, name, method, views):
     idx = rng.choice(g.n_vox, size=min(g.n_vox, 300 if name in ("c3", "c4") else 1500),
                      replace=False)
     ref_x = orc.adjoint(g, ys, method=method, voxels=idx)
-    assert rel_err(xb.reshape(-1)[idx], ref_x) <= TOL
+    e_b = rel_err(xb.reshape(-1)[idx], ref_x)
+    print(f"scan {name} {method}: forward err {e_f:.2e} "
+          f"({'all' if views is None else len(sel)} views), adjoint err {e_b:.2e} "
+          f"({len(idx)} voxels)", flush=True)
+    assert e_f <= TOL and e_b <= TOL
     plan.close()
