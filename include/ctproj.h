@@ -112,16 +112,20 @@ typedef struct ctp_plan ctp_plan;   /* opaque; immutable after creation */
 ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp_mode mode,
                            ctp_plan **out);
 
-/* Free the plan's device table.  The caller must ensure no call using it is in flight.
- * NULL is accepted. */
+/* Free the plan's device table (the counterpart of the geometry object's lifetime, Section
+ * 2.2; no computation).  The caller must ensure no call using it is in flight.  NULL is
+ * accepted. */
 ctp_status ctp_plan_destroy(ctp_plan *plan);
 
-/* Bytes of `batch` volumes and of `batch` sinograms stored as dtype. */
+/* Bytes of `batch` volumes and of `batch` sinograms stored as dtype: the device memory a
+ * caller (or the serving engine's admission) budgets for the data itself, which the library
+ * never copies out of the caller's buffers (zero-copy tensor sharing, Section 3.2). */
 ctp_status ctp_plan_bytes(const ctp_plan *plan, ctp_dtype dtype, int64_t batch,
                           size_t *vol_bytes, size_t *sino_bytes);
 
 /* Device workspace (bytes) that ctp_project (dir = CTP_FORWARD) or ctp_backproject
- * (CTP_BACKWARD) needs for `batch` items with the given storage types.  Forward: two floats
+ * (CTP_BACKWARD) needs for `batch` items with the given storage types: the per-call scratch of
+ * evaluating Eq. 1 / Eq. 2 on the device, which the caller owns.  Forward: two floats
  * per item for its accumulator scale, one float per 8192-element block of each item for its
  * max |x|, one z-fastest FP32 copy of the volume, and an FP32 sinogram when the sinogram is
  * BF16/FP16 (each part rounded up to 256 bytes).
@@ -198,10 +202,11 @@ ctp_status ctp_ramp_filter(const ctp_plan *plan, const void *sino, ctp_dtype sin
                            ctp_dtype out_dtype, int64_t batch, ctp_window window,
                            hipStream_t stream);
 
-/* Static description of a status code. */
+/* Static description of a status code (error reporting of the C boundary; no computation). */
 const char *ctp_status_string(ctp_status status);
 
-/* Thread-local detail message of the last failing call on this thread ("" if none). */
+/* Thread-local detail message of the last failing call on this thread ("" if none; error
+ * reporting of the C boundary, no computation). */
 const char *ctp_last_error(void);
 
 #ifdef __cplusplus

@@ -596,12 +596,11 @@ template <int K>
 __device__ __forceinline__ void nc_slot_weights(const float (&t)[4], float val, float eps,
                                                 float (&wv)[K + 1])
 {
-    float r1 = t[1] - t[0], r2 = t[3] - t[2];
+    // a ramp narrower than eps is a step: with the width floored at eps its quadratic part
+    // a^2 / (2 max(r, eps)) (a <= r) differs from the step's by less than eps / 2
+    const float r1 = t[1] - t[0], r2 = t[3] - t[2];
     const float rp = fmaxf(t[2] - t[1], 0.0f);
-    const bool s1 = r1 > eps, s2 = r2 > eps;
-    const float h1 = s1 ? 0.5f * fast_rcp(r1) : 0.0f, h2 = s2 ? 0.5f * fast_rcp(r2) : 0.0f;
-    r1 = s1 ? r1 : 0.0f;
-    r2 = s2 ? r2 : 0.0f;
+    const float h1 = 0.5f * fast_rcp(fmaxf(r1, eps)), h2 = 0.5f * fast_rcp(fmaxf(r2, eps));
     const float area = fmaf(0.5f, r1 + r2, rp);
     const float e0 = floorf(fmaxf(t[0], 0.0f));
     float G[K - 1];
@@ -2023,7 +2022,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         cval[k] = (cc >= 0 && cc < P.nu) ? 1.0f : 0.0f;
     }
     int jc = inside ? (int)floorf(p0) : (int)floorf(fminf(fmaxf(p0, -1.0f), (float)rows));
-    float nraw[K + 1], rc[K + 1], rp[K + 1], RP[K + 1], D2p[K + 1];
+    float nraw[K + 1], rc[K + 1], rp[K + 1], RP2[K + 1], D2p[K + 1];
     auto load_row = [&](int j, float (&dst)[K + 1]) {
         if (inside) {
             const float *rp_ = yv + (uint32_t)j * rs + (uint32_t)c_lo;
@@ -2043,7 +2042,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
 #pragma unroll
     for (int k = 0; k <= K; ++k) {
         rp[k] = 0.0f;
-        RP[k] = 0.0f;
+        RP2[k] = 0.0f;
         D2p[k] = 0.0f;
     }
     const float hamp = 0.5f * amp;         // D is carried doubled
@@ -2065,7 +2064,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         while (jc < jq) {
 #pragma unroll
             for (int k = 0; k <= K; ++k) {
-                RP[k] += rc[k];
+                RP2[k] = fmaf(2.0f, rc[k], RP2[k]);
                 rp[k] = rc[k];
                 rc[k] = nraw[k];
             }
@@ -2075,7 +2074,9 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         const float fjc = (float)jc;
         const float a = fmaxf(fjc - p, 0.0f);
         const float aw = (a * a) * fast_rcp(fmaxf(wf, 1e-30f));
-        const float qr = q - fjc;
+        // 2D = 2 (R(q) - J) = 2 (qr rc + RP) - (rp - rc) aw - rc wf: one line per cell, with
+        // the face's coefficients of rc and rp formed once (RP2 = 2 RP)
+        const float al = fmaf(2.0f, q - fjc, aw - wf), be = -aw;
         float wv[K + 1];
         if (f > 0) {
             nc_slot_weights<K>(tx, hamp, P.eps, wv);
@@ -2088,8 +2089,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         float s = 0.0f;
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
-            const float J2 = fmaf(rp[k] - rc[k], aw, rc[k] * wf);
-            const float D2 = fmaf(2.0f, fmaf(qr, rc[k], RP[k]), -J2);
+            const float D2 = fmaf(al, rc[k], fmaf(be, rp[k], RP2[k]));
             if (f > 0)
                 s = fmaf(wv[k], D2 - D2p[k], s);
             D2p[k] = D2;
