@@ -3,8 +3,9 @@
 // Forward (y = A x, Eq. 1) is output-stationary: a work-group owns one view and a strip of
 // kStripW detector columns, accumulates every row of that strip in LDS, and walks only the
 // voxel columns whose transaxial footprint meets the strip (tile culling, then per-column
-// test).  Inside a wavefront the lanes run along z of one voxel column (or, 32 lanes each, of
-// two), so a column's transaxial footprint is computed once and shared by its lanes, the axial
+// test).  Inside a wavefront the lanes run along z of one voxel column (or, 32 or 16 lanes
+// each, of two or four), so a column's transaxial footprint is computed once and shared by its
+// lanes, the axial
 // footprints of neighbouring lanes land in different detector rows (few LDS-atomic
 // collisions), and the volume, read from a z-fastest copy, is read with unit stride.  Each
 // strip is written once: no global atomics.
@@ -18,6 +19,12 @@
 //
 // Both directions call the same device functions for the footprint weights, so the pair is
 // matched up to the order of the FP32 sums.
+//
+// A launch covers the views [v_begin, v_begin + v_count) of its call: a call may be split
+// into launches over consecutive view ranges (the serving engine bounds how long one launch
+// holds the device).  Forward: each view's cells belong to that view's work-groups alone.
+// Back projection: launches after the first start each voxel's sum from the value the
+// previous one stored, so the split gives the single launch's bits.
 #include "engine.h"
 
 #include <hip/hip_bf16.h>
@@ -36,6 +43,15 @@
 #endif
 #ifndef CTP_FWD_PAIRS
 #define CTP_FWD_PAIRS 1   // forward: fast columns two per wavefront in runs of 8 slices
+#endif
+#ifndef CTP_FWD_WAVES
+#define CTP_FWD_WAVES 6   // forward, circular SF: wavefronts per SIMD the registers target
+#endif
+#ifndef CTP_FWD_QUADS
+#define CTP_FWD_QUADS 1   // forward: before the pairs, fast columns four per wavefront (16 slices)
+#endif
+#ifndef CTP_FWD_QUADS_DD
+#define CTP_FWD_QUADS_DD 1   // the same for the DD forward
 #endif
 #ifndef CTP_BWD_FAST
 #define CTP_BWD_FAST 1
@@ -873,18 +889,21 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 // INSIDE: the whole column projects into rows [0, R - 1) (checked per column, uniform), so the
 // row loops need no clamping to the row window.
 // NS: slices per lane (4: one column per wavefront, 64 runs per 256 slices; 8: two columns per
-// wavefront, lanes 0-31 and 32-63 each taking 256 slices of their own column in runs of 8).
+// wavefront, lanes 0-31 and 32-63 each taking 256 slices of their own column in runs of 8;
+// 16: four columns, 16 lanes each, in runs of 16).  Longer runs share their set-up and the
+// rows where neighbouring runs meet over more slices.
 // The column parameters may be uniform or per lane.  Every lane runs NS + 1 faces: when nz is
 // not a multiple of NS, the last run continues past the top slice with zero-valued slices on
 // the same face lines (the callers' fast and inside tests cover faces up to nz rounded up to a
-// multiple of 8), which only adds zero row values.
+// multiple of 8; runs of 16 are used only when nz is a multiple of 16), which only adds zero
+// row values.
 template <int K, int NC, bool NORM, bool INSIDE, int NS>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
                                            const float (&w)[K], int *accs, int SW, int R,
                                            int lane)
 {
-    static_assert(NS == 4 || NS == 8, "runs of 4 or 8 slices");
+    static_assert(NS == 4 || NS == 8 || NS == 16, "runs of 4, 8 or 16 slices");
     const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
     // every slice's trapezoid has the same area, the distance between consecutive face centres
     const float area = 0.5f * (bn + bf);
@@ -1023,7 +1042,7 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
 {
     // Every lane runs NS + 1 boundaries; past the top slice (nz not a multiple of NS) the run
     // continues with zero-valued slices, which only adds zero row values.
-    static_assert(NS == 4 || NS == 8, "runs of 4 or 8 slices");
+    static_assert(NS == 4 || NS == 8 || NS == 16, "runs of 4, 8 or 16 slices");
     const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
     const int l = lane & (256 / NS - 1);
     for (int zb = 0; zb < nz; zb += 256) {
@@ -1124,10 +1143,15 @@ __device__ __forceinline__ void fan2d_lane_scatter(const float *__restrict__ col
 #define CTP_FWD_THREADS 512
 #endif
 constexpr int kFwdThreads = CTP_FWD_THREADS;
+// Circular SF / recon-mode SF forward: 80 VGPRs for 6 wavefronts per SIMD (the LDS of three
+// 512-thread work-groups per CU allows 6), with the 16-slice runs of four columns per
+// wavefront; DD and non-circular keep the 128-VGPR target (measured faster or spill-free).
+template <int GEOM, int METHOD>
+constexpr int fwd_waves() { return GEOM == kCirc && METHOD != kDD ? CTP_FWD_WAVES : 4; }
 constexpr int kFwdWaves = kFwdThreads / 64;
 
 template <int GEOM, int DET, int METHOD, int K>
-__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4))) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd_waves<GEOM, METHOD>()))) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
                                                   const float *__restrict__ volT,
                                                   const float *__restrict__ qscale,
                                                   float *__restrict__ sino, int accumulate,
@@ -1289,6 +1313,42 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4))
                     // two fast columns at a time, lanes 0-31 on the first and 32-63 on the
                     // second, each lane running 8 slices and reading its column's record
                     uint64_t mp = m & m_fast;
+                    if (CTP_FWD_QUADS && (P.nz & 15) == 0) {
+                        // four fast columns at a time, 16 lanes each running 16 slices
+                        while (__popcll(mp) >= 4) {
+                            int cq[4];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                cq[i] = __ffsll((unsigned long long)mp) - 1;
+                                mp &= mp - 1ull;
+                                m &= ~(1ull << cq[i]);
+                            }
+                            const int src = lane < 32 ? (lane < 16 ? cq[0] : cq[1])
+                                                      : (lane < 48 ? cq[2] : cq[3]);
+                            const int p_nc = max(max(__float_as_int(rec[2][cq[0]]), __float_as_int(rec[2][cq[1]])),
+                                                 max(__float_as_int(rec[2][cq[2]]), __float_as_int(rec[2][cq[3]])));
+                            const bool p_inside = ((m_inside >> cq[0]) & (m_inside >> cq[1]) &
+                                                   (m_inside >> cq[2]) & (m_inside >> cq[3]) & 1ull) != 0;
+                            const int l_col = __float_as_int(rec[0][src]);
+                            const int l_slot = __float_as_int(rec[1][src]);
+                            float lw[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k)
+                                lw[k] = rec[7 + k][src];
+                            const float l_an = rec[3][src], l_bn = rec[4][src];
+                            const float l_af = rec[5][src], l_bf = rec[6][src];
+                            const float *colp = volb + (int64_t)l_col * colstride;
+                            int *accs = acc + l_slot;
+                            if (p_inside)
+                                sf_fwd_run_nc<K, METHOD == kSFR, true, 16>(colp, P.nz, l_an, l_bn, l_af,
+                                                                           l_bf, lw, p_nc, accs, SW, R,
+                                                                           lane);
+                            else
+                                sf_fwd_run_nc<K, METHOD == kSFR, false, 16>(colp, P.nz, l_an, l_bn, l_af,
+                                                                            l_bf, lw, p_nc, accs, SW, R,
+                                                                            lane);
+                        }
+                    }
                     while (__popcll(mp) >= 2) {
                         const int c1 = __ffsll((unsigned long long)mp) - 1;
                         mp &= mp - 1ull;
@@ -1538,6 +1598,32 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4))
                         rec[3 + K + k][lane] = bz[k];
                     }
                     if constexpr (CTP_FWD_PAIRS) {
+                        if (CTP_FWD_QUADS_DD && (P.nz & 15) == 0) {
+                            // four columns at a time, 16 lanes each running 16 slices
+                            while (__popcll(m) >= 4) {
+                                int cq[4];
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    cq[i] = __ffsll((unsigned long long)m) - 1;
+                                    m &= m - 1ull;
+                                }
+                                const int src = lane < 32 ? (lane < 16 ? cq[0] : cq[1])
+                                                          : (lane < 48 ? cq[2] : cq[3]);
+                                const int p_nc = max(max(__float_as_int(rec[2][cq[0]]), __float_as_int(rec[2][cq[1]])),
+                                                     max(__float_as_int(rec[2][cq[2]]), __float_as_int(rec[2][cq[3]])));
+                                float lfx[K], lal[K], lbe[K];
+#pragma unroll
+                                for (int k = 0; k < K; ++k) {
+                                    lfx[k] = rec[3 + k][src];
+                                    const float bk = rec[3 + K + k][src];
+                                    lal[k] = fmaf(bk, zb0, V.ddC - (float)r0);
+                                    lbe[k] = bk * P.dz;
+                                }
+                                const float *colp = volb + (int64_t)__float_as_int(rec[0][src]) * colstride;
+                                int *accs = acc + __float_as_int(rec[1][src]);
+                                dd_fwd_run<K, 16>(colp, P.nz, lal, lbe, lfx, p_nc, accs, SW, R, lane);
+                            }
+                        }
                         while (__popcll(m) >= 2) {
                             const int c1 = __ffsll((unsigned long long)m) - 1;
                             m &= m - 1ull;

@@ -261,13 +261,15 @@ def test_long_columns_and_strong_cone(torch_gpu, orc, method):
     assert rel_err(run_fwd(torch_gpu, plan2, x2), orc.forward(g2, x2, method=method)) <= TOL
 
 
-@pytest.mark.parametrize("nz", [36, 260])
+@pytest.mark.parametrize("nz", [36, 48, 260, 272])
 @pytest.mark.parametrize("det,method,mode", [("flat", "sf", "proj"), ("curved", "sf", "proj"),
                                              ("flat", "dd", "proj"), ("flat", "sf", "recon")])
 def test_run_lengths(torch_gpu, orc, nz, det, method, mode):
     """Columns whose length is a multiple of 4 but not of 8 (the forward's 8-slice runs of
     paired columns end with zero-valued slices past the top one), in one pass (36) and in two
-    256-slice passes (260); the back projection's last z-chunk is partial in both."""
+    256-slice passes (260), and multiples of 16 (four columns per wavefront in 16-slice runs:
+    48, and 272 with a second pass of one run per column); the back projection's last z-chunk
+    is partial in all but 48 and 272."""
     from paper_2503_16741_amd import ctproj
     print(f"case nz={nz} {det}/{method}/{mode}", flush=True)
     g = synth.Geometry(kind="cone", det=det, nx=10, ny=9, nz=nz, dx=1.0, dy=1.0,
