@@ -1105,8 +1105,13 @@ __device__ __forceinline__ void dd_fwd_run(const float *__restrict__ colp, int n
 }
 
 // Non-circular SF forward: column runs of kNCRun slices for footprints of at most 4 cells
-// (the run's cells then fit K + 1 slots), otherwise the per-voxel loop only.
-constexpr int kNCRun = 8;
+// (the run's cells then fit K + 1 slots), otherwise the per-voxel loop only.  The plan bounds
+// the expansion error and the drift over runs of kNCRunMax = 16 slices.
+#ifndef CTP_NC_RUN
+#define CTP_NC_RUN 16
+#endif
+constexpr int kNCRun = CTP_NC_RUN;
+static_assert(kNCRun <= kNCRunMax, "the plan bounds runs of at most kNCRunMax slices");
 template <int GEOM, int METHOD, int K>
 constexpr bool nc_fwd_runs() { return GEOM == kNonCirc && METHOD == kSF && K <= 4 && CTP_FWD_FAST; }
 // Forward LDS row: the strip plus one padding column; the non-circular runs add K columns on
