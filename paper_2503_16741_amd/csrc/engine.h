@@ -86,6 +86,9 @@ struct Params {
     // views [v_begin, v_begin + v_count) of a forward or back projection launch (a call may
     // be split into several launches over consecutive view ranges); 0, n_views for a whole call
     int v_begin, v_count;
+    // 3D: some view projects part of the volume beyond the detector rows (the back projection
+    // then tests each chunk for faces that miss them all)
+    int row_clip;
 };
 
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.

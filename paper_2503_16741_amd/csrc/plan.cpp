@@ -202,6 +202,7 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     // projection over a run, and how far a footprint drifts along a run (columns)
     double nc_rem = 0.0, nc_drift = 0.0;
     double rmax = 0.0;   // recon mode: largest SAD / W over views and volume corners
+    bool row_clip = false;  // a volume corner projects beyond the detector rows in some view
     double mmin = 1e300; // smallest magnification over views and volume corners
 
     for (int b = 0; b < g.n_views; ++b) {
@@ -239,6 +240,18 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
         if (!(Wmin > 1e-6 * f.sdd))
             return fail(CTP_EINVAL, "part of the volume is at or behind the source in view " + std::to_string(b));
         rmax = std::fmax(rmax, sad.at(b) / Wmin);
+        if (!two_d) {
+            for (int c = 0; c < 8; ++c) {
+                const Vec3 p{(c & 1) ? hx : -hx, (c & 2) ? hy : -hy, (c & 4) ? hz : -hz};
+                const double W = dot(f.s - p, f.n), h = dot(p - f.s, f.ev);
+                const double a = dot(p - f.s, f.eu);
+                const double v = dot(f.s - f.d, f.ev) +
+                                 (g.det == CTP_DET_FLAT ? dot(f.s - f.d, f.n) * h / W
+                                                        : f.sdd * h / std::hypot(a, W));
+                const double row = (v - f.ve0) / g.dv;
+                row_clip = row_clip || row < 0.0 || row > (double)nv;
+            }
+        }
         mmin = std::fmin(mmin, (g.det == CTP_DET_FLAT ? D : f.sdd) / std::hypot(Wmax, amax));
 
         // bound on the transaxial footprint width (columns): |grad u| * voxel extent
@@ -384,6 +397,7 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     p.n_views = g.n_views;
     p.v_begin = 0;
     p.v_count = g.n_views;
+    p.row_clip = row_clip ? 1 : 0;
     p.eps = 1e-6f;
     // non-circular SF column runs: expansion accurate to 2e-5 cells / rows, a run's footprints
     // within K + 1 cells (their union is narrower than K: widths below K - 1 plus the drift)
