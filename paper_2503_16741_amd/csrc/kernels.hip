@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <map>
 #include <mutex>
 
@@ -49,6 +50,9 @@
 #endif
 #ifndef CTP_FWD_QUADS
 #define CTP_FWD_QUADS 1   // forward: before the pairs, fast columns four per wavefront (16 slices)
+#endif
+#ifndef CTP_FWD_ITEMS
+#define CTP_FWD_ITEMS 1   // forward: (column, run) items for columns beyond the row window
 #endif
 #ifndef CTP_FWD_QUADS_DD
 #define CTP_FWD_QUADS_DD 1   // the same for the DD forward
@@ -903,6 +907,109 @@ __device__ __forceinline__ bool sf_fast_ok(float an, float bn, float af, float b
 // the same face lines (the callers' fast and inside tests cover faces up to nz rounded up to a
 // multiple of 8; runs of 16 are used only when nz is a multiple of 16), which only adds zero
 // row values.
+// One run of NS slices of a column, from slice z0 (the body of sf_fwd_run, also used for the
+// (column, run) items of columns that reach beyond the row window).  area: the slices' common
+// trapezoid area (rows), inv_area its reciprocal (recon mode).
+template <int K, int NC, bool NORM, bool INSIDE, int NS>
+__device__ __forceinline__ void sf_fwd_run_at(const float *__restrict__ colp, int nz, int z0,
+                                              float an, float bn, float af, float bf,
+                                              float area, float inv_area, const float (&w)[K],
+                                              int *accs, int SW, int R)
+{
+    const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
+    // faces z0 .. z0 + NS on the near and far lines, in rows relative to the run's base
+    // row edge (the subtraction is exact), so the face offsets within the run and the row
+    // edges are accurate to a few ulps of the run's extent rather than of the row index
+    const float z0f = (float)z0;
+    const float an0 = fmaf(bn, z0f, an), af0 = fmaf(bf, z0f, af);
+    const float base = floorf(fminf(an0, af0));
+    const float an0r = an0 - base, af0r = af0 - base;
+    // faces are formed as the walk reaches them (face f: [pf(f), qf(f)]), which keeps
+    // few of them live at once
+    auto pf = [&](int f) {
+        return f == 0 ? fminf(an0r, af0r) : fminf(fmaf((float)f, bn, an0r), fmaf((float)f, bf, af0r));
+    };
+    auto qff = [&](int f) {
+        return f == 0 ? fmaxf(an0r, af0r) : fmaxf(fmaf((float)f, bn, an0r), fmaf((float)f, bf, af0r));
+    };
+    // skip runs entirely outside the row window (before loading their slices)
+    if (!INSIDE && (qff(NS) < -base || base >= fR))
+        return;
+    float v[NS];
+    if ((nz & 3) == 0) {
+#pragma unroll
+        for (int g = 0; g < NS; g += 4) {
+            const float4 v4 = z0 + g < nz ? *reinterpret_cast<const float4 *>(colp + z0 + g)
+                                          : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            v[g] = v4.x; v[g + 1] = v4.y; v[g + 2] = v4.z; v[g + 3] = v4.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
+    }
+    if constexpr (NORM) {   // recon mode: each voxel's axial trapezoid normalised to unit area
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            v[q] *= inv_area;
+    }
+    // ft: the next row edge to close (relative; row base + ft - 1, row -1 being the guard
+    // row), ap: that row.  cp: C at the previous edge minus the prefix S_q of the current
+    // face q, so that the row value is local(t) - cp with local(t) = C(t) - S_q a sum of a
+    // few small terms.
+    float ft = INSIDE ? 1.0f : fmaxf(base, -1.0f) + 1.0f - base;
+    int *ap = accs - SW + __umul24((unsigned)(ft + base), SW);
+    const float lim1 = fR1 - base, limm1 = fRm1 - base;   // row window (relative)
+    float cp = 0.0f;
+    auto emit = [&](float local) {
+        const float rv = local - cp;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            atomicAdd(ap + k, to_fixed(rv * w[k]));
+        cp = local;
+        ap += SW;
+        ft += 1.0f;
+    };
+    // Inside face q (or on voxel q's plateau above it), with u = t - q_q, e = max(u, 0),
+    // d2 = e - u = max(q_q - t, 0) and d1 = w_q - d2 = min(t - p_q, w_q):
+    //   local = v_q (d1^2 / (2 w_q) + e) - v_{q-1} d2^2 / (2 w_q)
+    float pc = pf(0), qc = qff(0);   // current face
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const float pn = pf(q + 1);
+        const float wq = qc - pc;
+        const float h = 0.5f * fast_rcp(fmaxf(wq, 1e-30f));
+        const float fte = INSIDE ? ceilf(pn) - 1.0f : ceilf(fminf(pn, lim1)) - 1.0f;
+        if (q == 0) {   // no voxel below the run
+            while (ft <= fte) {
+                const float u = ft - qc, e = fmaxf(u, 0.0f);
+                const float d1 = wq - (e - u);
+                emit(v[0] * fmaf(d1 * d1, h, e));
+            }
+        } else {
+            const float nvh = -v[q - 1] * h;
+            while (ft <= fte) {
+                const float u = ft - qc, e = fmaxf(u, 0.0f);
+                const float d2 = e - u, d1 = wq - d2;
+                emit(fmaf(v[q], fmaf(d1 * d1, h, e), (d2 * d2) * nvh));
+            }
+        }
+        cp = fmaf(-v[q], area, cp);   // S_{q+1} = S_q + v_q area
+        pc = pn;
+        qc = qff(q + 1);
+    }
+    // above the run's top face: the last voxel's falling ramp over face NS
+    {
+        const float h = 0.5f * fast_rcp(fmaxf(qc - pc, 1e-30f));
+        const float nvh = -v[NS - 1] * h;
+        const float fte = INSIDE ? floorf(qc) + 1.0f : floorf(fminf(qc, limm1)) + 1.0f;
+        while (ft <= fte) {
+            const float d2 = fmaxf(qc - ft, 0.0f);
+            emit((d2 * d2) * nvh);
+        }
+    }
+}
+
 template <int K, int NC, bool NORM, bool INSIDE, int NS>
 __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int nz, float an,
                                            float bn, float af, float bf,
@@ -910,7 +1017,6 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
                                            int lane)
 {
     static_assert(NS == 4 || NS == 8 || NS == 16, "runs of 4, 8 or 16 slices");
-    const float fR = (float)R, fR1 = (float)(R + 1), fRm1 = (float)(R - 1);
     // every slice's trapezoid has the same area, the distance between consecutive face centres
     const float area = 0.5f * (bn + bf);
     const float inv_area = NORM ? fast_rcp(area) : 1.0f;
@@ -919,97 +1025,8 @@ __device__ __forceinline__ void sf_fwd_run(const float *__restrict__ colp, int n
         const int z0 = zb + NS * l;
         if (z0 >= nz)
             break;
-        // faces z0 .. z0 + NS on the near and far lines, in rows relative to the run's base
-        // row edge (the subtraction is exact), so the face offsets within the run and the row
-        // edges are accurate to a few ulps of the run's extent rather than of the row index
-        const float z0f = (float)z0;
-        const float an0 = fmaf(bn, z0f, an), af0 = fmaf(bf, z0f, af);
-        const float base = floorf(fminf(an0, af0));
-        const float an0r = an0 - base, af0r = af0 - base;
-        // faces are formed as the walk reaches them (face f: [pf(f), qf(f)]), which keeps
-        // few of them live at once
-        auto pf = [&](int f) {
-            return f == 0 ? fminf(an0r, af0r) : fminf(fmaf((float)f, bn, an0r), fmaf((float)f, bf, af0r));
-        };
-        auto qff = [&](int f) {
-            return f == 0 ? fmaxf(an0r, af0r) : fmaxf(fmaf((float)f, bn, an0r), fmaf((float)f, bf, af0r));
-        };
-        // skip runs entirely outside the row window (before loading their slices)
-        if (!INSIDE && (qff(NS) < -base || base >= fR))
-            continue;
-        float v[NS];
-        if ((nz & 3) == 0) {
-#pragma unroll
-            for (int g = 0; g < NS; g += 4) {
-                const float4 v4 = z0 + g < nz ? *reinterpret_cast<const float4 *>(colp + z0 + g)
-                                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                v[g] = v4.x; v[g + 1] = v4.y; v[g + 2] = v4.z; v[g + 3] = v4.w;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < NS; ++q)
-                v[q] = z0 + q < nz ? colp[z0 + q] : 0.0f;
-        }
-        if constexpr (NORM) {   // recon mode: each voxel's axial trapezoid normalised to unit area
-#pragma unroll
-            for (int q = 0; q < NS; ++q)
-                v[q] *= inv_area;
-        }
-        // ft: the next row edge to close (relative; row base + ft - 1, row -1 being the guard
-        // row), ap: that row.  cp: C at the previous edge minus the prefix S_q of the current
-        // face q, so that the row value is local(t) - cp with local(t) = C(t) - S_q a sum of a
-        // few small terms.
-        float ft = INSIDE ? 1.0f : fmaxf(base, -1.0f) + 1.0f - base;
-        int *ap = accs - SW + __umul24((unsigned)(ft + base), SW);
-        const float lim1 = fR1 - base, limm1 = fRm1 - base;   // row window (relative)
-        float cp = 0.0f;
-        auto emit = [&](float local) {
-            const float rv = local - cp;
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-                atomicAdd(ap + k, to_fixed(rv * w[k]));
-            cp = local;
-            ap += SW;
-            ft += 1.0f;
-        };
-        // Inside face q (or on voxel q's plateau above it), with u = t - q_q, e = max(u, 0),
-        // d2 = e - u = max(q_q - t, 0) and d1 = w_q - d2 = min(t - p_q, w_q):
-        //   local = v_q (d1^2 / (2 w_q) + e) - v_{q-1} d2^2 / (2 w_q)
-        float pc = pf(0), qc = qff(0);   // current face
-#pragma unroll
-        for (int q = 0; q < NS; ++q) {
-            const float pn = pf(q + 1);
-            const float wq = qc - pc;
-            const float h = 0.5f * fast_rcp(fmaxf(wq, 1e-30f));
-            const float fte = INSIDE ? ceilf(pn) - 1.0f : ceilf(fminf(pn, lim1)) - 1.0f;
-            if (q == 0) {   // no voxel below the run
-                while (ft <= fte) {
-                    const float u = ft - qc, e = fmaxf(u, 0.0f);
-                    const float d1 = wq - (e - u);
-                    emit(v[0] * fmaf(d1 * d1, h, e));
-                }
-            } else {
-                const float nvh = -v[q - 1] * h;
-                while (ft <= fte) {
-                    const float u = ft - qc, e = fmaxf(u, 0.0f);
-                    const float d2 = e - u, d1 = wq - d2;
-                    emit(fmaf(v[q], fmaf(d1 * d1, h, e), (d2 * d2) * nvh));
-                }
-            }
-            cp = fmaf(-v[q], area, cp);   // S_{q+1} = S_q + v_q area
-            pc = pn;
-            qc = qff(q + 1);
-        }
-        // above the run's top face: the last voxel's falling ramp over face NS
-        {
-            const float h = 0.5f * fast_rcp(fmaxf(qc - pc, 1e-30f));
-            const float nvh = -v[NS - 1] * h;
-            const float fte = INSIDE ? floorf(qc) + 1.0f : floorf(fminf(qc, limm1)) + 1.0f;
-            while (ft <= fte) {
-                const float d2 = fmaxf(qc - ft, 0.0f);
-                emit((d2 * d2) * nvh);
-            }
-        }
+        sf_fwd_run_at<K, NC, NORM, INSIDE, NS>(colp, nz, z0, an, bn, af, bf, area, inv_area, w,
+                                               accs, SW, R);
     }
 }
 
@@ -1320,6 +1337,86 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
                         rec[7 + k][lane] = w[k];
                 }
                 uint64_t m = __ballot(nc > 0);
+                if constexpr (STAGE && CTP_FWD_ITEMS) {
+                    if ((P.nz & 15) == 0 && (m_fast & ~m_inside) != 0) {
+                        // some fast columns reach beyond the row window (a volume taller than
+                        // the detector's reach): only the 16-slice runs of the fast columns
+                        // whose faces can meet the window become (column, run) items, spread
+                        // over the lanes (an exclusive scan of the run counts, a binary
+                        // search per item); every run still tests its own rows
+                        const int nrun = P.nz >> 4;
+                        int rlo = 0, nr = 0;
+                        if ((m_fast >> lane) & 1ull) {
+                            // faces f with q(f) >= 0 start after fq, faces with p(f) < R end
+                            // before fp (both lines increase); a run covers faces 16r..16r+16
+                            const float fq = fminf(-an / bn, -af / bf);
+                            const float fp = fmaxf(((float)R - an) / bn, ((float)R - af) / bf);
+                            rlo = max((int)floorf(fmaxf(fq, -1.0e6f) * (1.0f / 16.0f)) - 2, 0);
+                            const int rhi = min((int)floorf(fminf(fp, 1.0e6f) * (1.0f / 16.0f)) + 1,
+                                                nrun - 1);
+                            nr = max(rhi - rlo + 1, 0);
+                        }
+                        int incl = nr;
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1) {
+                            const int t = __shfl_up(incl, d);
+                            if (lane >= d)
+                                incl += t;
+                        }
+                        const int excl = incl - nr;
+                        const int items = __shfl(incl, 63);
+                        // the emit width: the widest fast column's cell count
+                        int wnc = ((m_fast >> lane) & 1ull) ? nc : 0;
+#pragma unroll
+                        for (int d = 32; d >= 1; d >>= 1)
+                            wnc = max(wnc, __shfl_xor(wnc, d));
+                        auto run_items = [&](auto ncc) {
+                            constexpr int NC = decltype(ncc)::value;
+                            for (int b0 = 0; b0 < items; b0 += 64) {
+                                const int it = b0 + lane;
+                                // the last column whose first item is at most it: a binary
+                                // search over the lanes' exclusive sums, six steps taken by
+                                // every lane (the shuffles read from all lanes)
+                                int src = 0;
+#pragma unroll
+                                for (int step = 32; step >= 1; step >>= 1) {
+                                    const int mid = src + step;
+                                    const int e = __shfl(excl, min(mid, 63));
+                                    if (mid < 64 && e <= it)
+                                        src = mid;
+                                }
+                                const int run = __shfl(rlo, src) + (it - __shfl(excl, src));
+                                if (it < items) {
+                                    float lw[K];
+#pragma unroll
+                                    for (int k = 0; k < K; ++k)
+                                        lw[k] = rec[7 + k][src];
+                                    const float l_an = rec[3][src], l_bn = rec[4][src];
+                                    const float l_af = rec[5][src], l_bf = rec[6][src];
+                                    const float area = 0.5f * (l_bn + l_bf);
+                                    const float *colp = volb + (int64_t)__float_as_int(rec[0][src]) * colstride;
+                                    sf_fwd_run_at<K, NC, METHOD == kSFR, false, 16>(
+                                        colp, P.nz, 16 * run, l_an, l_bn, l_af, l_bf, area,
+                                        METHOD == kSFR ? fast_rcp(area) : 1.0f, lw,
+                                        acc + __float_as_int(rec[1][src]), SW, R);
+                                }
+                            }
+                        };
+                        if constexpr (K <= 4) {
+                            if (wnc <= 1)
+                                run_items(std::integral_constant<int, 1>{});
+                            else if (wnc == 2)
+                                run_items(std::integral_constant<int, (K >= 2 ? 2 : K)>{});
+                            else if (wnc == 3)
+                                run_items(std::integral_constant<int, (K >= 3 ? 3 : K)>{});
+                            else
+                                run_items(std::integral_constant<int, K>{});
+                        } else {
+                            run_items(std::integral_constant<int, K>{});
+                        }
+                        m &= ~m_fast;
+                    }
+                }
                 if constexpr (STAGE && CTP_FWD_PAIRS) {
                     // two fast columns at a time, lanes 0-31 on the first and 32-63 on the
                     // second, each lane running 8 slices and reading its column's record

@@ -284,6 +284,45 @@ def test_run_lengths(torch_gpu, orc, nz, det, method, mode):
                    orc.adjoint(g, y, method=method, mode=mode)) <= TOL
 
 
+@pytest.mark.parametrize("det,method,mode", [("flat", "sf", "proj"), ("curved", "sf", "proj"),
+                                             ("flat", "sf", "recon"), ("flat", "dd", "proj")])
+def test_volume_taller_than_the_detector_reach(torch_gpu, orc, det, method, mode):
+    """A 64-slice volume on a 24-row detector: most voxel columns reach beyond the rows, so the
+    forward pass takes the (column, run) items of the runs that can meet the rows and the back
+    projection skips the chunks whose faces miss them (the plan sees the volume pass the rows);
+    nz = 64 also spreads the back projection's z-chunks over the XCDs only when there are 8 of
+    them (here 4: the contiguous order)."""
+    from paper_2503_16741_amd import ctproj
+    print(f"case tall {det}/{method}/{mode}", flush=True)
+    g = synth.Geometry(kind="cone", det=det, nx=30, ny=26, nz=64, dx=0.8, dy=0.8, dz=0.8,
+                       nu=90, nv=24, du=0.9, dv=0.9, n_views=7, theta=synth.full_circle(7) + 0.3,
+                       sad=250.0, sdd=400.0, z_ofst=1.1)
+    plan = ctproj.ctp_plan_create(g, method, mode)
+    x = synth.random_volume(g, seed=40)
+    assert rel_err(run_fwd(torch_gpu, plan, x),
+                   orc.forward(g, x, method=method, mode=mode)) <= TOL
+    y = synth.random_sinogram(g, seed=41)
+    assert rel_err(run_bwd(torch_gpu, plan, y),
+                   orc.adjoint(g, y, method=method, mode=mode)) <= TOL
+
+
+def test_tall_volume_z_chunks_spread(torch_gpu, orc):
+    """256 slices (16 back-projection z-chunks, spread over the XCDs) on a 40-row detector: the
+    sampled adjoint and the forward on sampled views against the oracle."""
+    from paper_2503_16741_amd import ctproj
+    g = synth.Geometry(kind="cone", det="flat", nx=20, ny=20, nz=256, dx=0.5, dy=0.5, dz=0.5,
+                       nu=64, nv=40, du=0.8, dv=0.8, n_views=5, theta=synth.full_circle(5),
+                       sad=300.0, sdd=480.0)
+    for method in ("sf", "dd"):
+        print(f"case tall 256 {method}", flush=True)
+        plan = ctproj.ctp_plan_create(g, method)
+        x = synth.random_volume(g, seed=42)
+        assert rel_err(run_fwd(torch_gpu, plan, x), orc.forward(g, x, method=method)) <= TOL
+        y = synth.random_sinogram(g, seed=43)
+        assert rel_err(run_bwd(torch_gpu, plan, y), orc.adjoint(g, y, method=method)) <= TOL
+        plan.close()
+
+
 @pytest.mark.parametrize("du,nu", [(0.45, 100), (0.25, 160)])
 @pytest.mark.parametrize("method", ["sf", "dd"])
 def test_wide_footprints(torch_gpu, orc, du, nu, method):
