@@ -48,6 +48,9 @@
 #ifndef CTP_FWD_WAVES
 #define CTP_FWD_WAVES 6   // forward, circular SF: wavefronts per SIMD the registers target
 #endif
+#ifndef CTP_FWD_WAVES_NC
+#define CTP_FWD_WAVES_NC 4   // forward, non-circular: wavefronts per SIMD the registers target
+#endif
 #ifndef CTP_FWD_QUADS
 #define CTP_FWD_QUADS 1   // forward: before the pairs, fast columns four per wavefront (16 slices)
 #endif
@@ -57,11 +60,20 @@
 #ifndef CTP_FWD_QUADS_DD
 #define CTP_FWD_QUADS_DD 1   // the same for the DD forward
 #endif
+#ifndef CTP_FWD_LANEORD
+#define CTP_FWD_LANEORD 1   // forward: tile lanes along the axis where u changes most, spaced
+#endif
 #ifndef CTP_BWD_ZSPREAD
 #define CTP_BWD_ZSPREAD 1   // back projection: z-chunks spread over the XCDs (see bwd_kernel)
 #endif
 #ifndef CTP_BWD_SKIP
 #define CTP_BWD_SKIP 1      // back projection: chunks whose faces miss the detector rows skip
+#endif
+#ifndef CTP_BWD_INSIDE_WAVE
+#define CTP_BWD_INSIDE_WAVE 1   // back projection: the clamped walk for the whole wavefront
+#endif
+#ifndef CTP_BWD_PRESKIP
+#define CTP_BWD_PRESKIP 1   // back projection: a cheaper skip test before the column set-up
 #endif
 #ifndef CTP_BWD_FAST
 #define CTP_BWD_FAST 1
@@ -1175,7 +1187,10 @@ constexpr int kFwdThreads = CTP_FWD_THREADS;
 // 512-thread work-groups per CU allows 6), with the 16-slice runs of four columns per
 // wavefront; DD and non-circular keep the 128-VGPR target (measured faster or spill-free).
 template <int GEOM, int METHOD>
-constexpr int fwd_waves() { return GEOM == kCirc && METHOD != kDD ? CTP_FWD_WAVES : 4; }
+constexpr int fwd_waves()
+{
+    return GEOM == kCirc && METHOD != kDD ? CTP_FWD_WAVES : GEOM == kNonCirc ? CTP_FWD_WAVES_NC : 4;
+}
 constexpr int kFwdWaves = kFwdThreads / 64;
 
 template <int GEOM, int DET, int METHOD, int K>
@@ -1285,8 +1300,17 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
                 break;
             const int t = t0 + s_list[h];
             const int tx = t % tiles_x, ty = t / tiles_x;
-            const int ix = tx * kTile + (lane & (kTile - 1));
-            const int iy = ty * kTile + (lane >> 3);
+            // lanes -> columns of the 8 x 8 tile: along the axis on which u changes most in
+            // this view, every other column first (0, 2, 4, 6, 1, 3, 5, 7), so that the
+            // columns walked together in one wavefront (four or two at a time, or the runs of
+            // neighbouring columns) project at least ~1.4 cells apart and their same-row
+            // atomics rarely meet at one LDS address (sums are integers: any order gives
+            // the same bits)
+            const int la = lane & (kTile - 1), lb = lane >> 3;
+            const int lmaj = CTP_FWD_LANEORD ? ((la & 3) << 1) | (la >> 2) : la;
+            const bool ymaj = CTP_FWD_LANEORD && fabsf(V.eu[1]) > fabsf(V.eu[0]);
+            const int ix = tx * kTile + (ymaj ? lb : lmaj);
+            const int iy = ty * kTile + (ymaj ? lmaj : lb);
             const bool valid = ix < P.nx && iy < P.ny;
             const float xc = fmaf((float)ix, P.dx, P.x0), yc = fmaf((float)iy, P.dy, P.y0);
 
@@ -2000,8 +2024,11 @@ __device__ __forceinline__ void sf_circ_gather(const Params &P, const float *__r
         const float z0f = (float)zc0, z1f = (float)(zc0 + kZChunk);
         const float plo = fminf(fmaf(bn, z0f, an), fmaf(bf, z0f, af));
         const float qhi = fmaxf(fmaf(bn, z1f, an), fmaf(bf, z1f, af));
-        const bool inside = plo >= 0.0f && qhi < (float)(rows_total - 2) &&
-                            cs + K <= P.nu;
+        bool inside = plo >= 0.0f && qhi < (float)(rows_total - 2) && cs + K <= P.nu;
+        // one walk per wavefront: when some of its lanes need the clamped walk, all take it
+        // (else the wavefront would run both, one after the other)
+        if (CTP_BWD_INSIDE_WAVE)
+            inside = __ballot(inside) == __ballot(true);
         if (inside)
             sf_bwd_fast<K, kZChunk, NORM, true>(
                 yv, P.sino_row_stride, cs, P.nu, rows_total, w, an, bn, af, bf,
@@ -2307,8 +2334,14 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
 #ifndef CTP_BWD_SF_BLOCKS
 #define CTP_BWD_SF_BLOCKS 8
 #endif
+#ifndef CTP_BWD_NC_BLOCKS
+#define CTP_BWD_NC_BLOCKS 1
+#endif
 template <int GEOM, int METHOD>
-constexpr int bwd_min_blocks() { return GEOM == kCirc && METHOD != kDD ? CTP_BWD_SF_BLOCKS : 1; }
+constexpr int bwd_min_blocks()
+{
+    return GEOM == kCirc && METHOD != kDD ? CTP_BWD_SF_BLOCKS : GEOM == kNonCirc ? CTP_BWD_NC_BLOCKS : 1;
+}
 
 // Whether the back projection spreads its z-chunks over the XCDs (see bwd_kernel): SF always
 // (measured 2 % faster on 256^3 x 360), DD only when the volume reaches beyond the detector
@@ -2360,6 +2393,7 @@ __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_ker
     const bool valid = ix < P.nx && iy < P.ny;
     const float xc = fmaf((float)ix, P.dx, P.x0), yc = fmaf((float)iy, P.dy, P.y0);
     const float hz = 0.5f * P.dz;
+    const float rdiag = 0.5f * sqrtf(fmaf(P.dx, P.dx, P.dy * P.dy));   // half-diagonal (xy)
     const float *ysb = ys + (int64_t)b * P.sino_b_stride;
     const int nzv = P.nz;
     const int rows_total = GEOM == kFan2D ? P.nz : P.nv;
@@ -2385,6 +2419,29 @@ __global__ __launch_bounds__(256, (bwd_min_blocks<GEOM, METHOD>())) void bwd_ker
             const float zb0 = P.z0 - hz - V.s[2];
 
             if constexpr (METHOD != kDD && GEOM != kNonCirc) {
+                if (GEOM != kFan2D && DET == kCurved && CTP_BWD_SKIP && CTP_BWD_PRESKIP &&
+                    P.row_clip) {
+                    // before the curved detector's transaxial set-up (five arc tangents): the
+                    // corners' distances from the source in the transaxial plane lie within
+                    // rdiag of the centre's M, so the column's axial lines v = cv + A h have
+                    // slopes A in [Dv / (M + rdiag), Dv / (M - rdiag)]; when every such line
+                    // misses the detector rows over the chunk's face heights h, so do the
+                    // column's own (bilinear in A and h: the extremes lie at the corners).
+                    // (On a flat detector the set-up is cheap and the test measured slower.)
+                    const float ac = fmaf(xc, V.eu[0], fmaf(yc, V.eu[1], -V.seu));
+                    const float Wc = V.sn - fmaf(xc, V.n[0], yc * V.n[1]);
+                    const float M = sqrtf(fmaf(ac, ac, Wc * Wc));
+                    if (M > 2.0f * rdiag) {
+                        const float Ahi = fdiv(V.Dv, M - rdiag), Alo = fdiv(V.Dv, M + rdiag);
+                        const float h0 = fmaf((float)zc0, P.dz, zb0);
+                        const float h1 = fmaf((float)(zc0 + kZChunk), P.dz, zb0);
+                        const float vlo = V.cv + fminf(fminf(Ahi * h0, Alo * h0), fminf(Ahi * h1, Alo * h1));
+                        const float vhi = V.cv + fmaxf(fmaxf(Ahi * h0, Alo * h0), fmaxf(Ahi * h1, Alo * h1));
+                        // a margin of 1/64 row covers the rounding of both tests
+                        if (vhi < -0.015625f || vlo >= (float)rows_total + 0.015625f)
+                            continue;
+                    }
+                }
                 SFCol col;
                 sf_column<DET>(V, P, xc, yc, 0.0f, col);
                 if constexpr (METHOD == kSFR)
