@@ -116,6 +116,18 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // coordinate whose FP32 rounding is already larger.
 __device__ __forceinline__ float fdiv(float a, float b) { return a * fast_rcp(b); }
 
+// atan2(y, x) of a small angle: for x > 0 and |y| < x / 64 the series r - r^3 / 3 of r = y / x,
+// whose first omitted term r^5 / 5 stays below a 1e-8 part of the result (under half an FP32
+// ulp); otherwise atan2f.
+__device__ __forceinline__ float atan2_small(float y, float x)
+{
+    if (x > 0.0f && fabsf(y) < 0.015625f * x) {
+        const float r = fdiv(y, x);
+        return r * fmaf(-0.333333343f, r * r, 1.0f);
+    }
+    return atan2f(y, x);
+}
+
 __device__ __forceinline__ float readlane_f(float v, int lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -211,11 +223,13 @@ __device__ __forceinline__ void sf_column(const ViewRec &V, const Params &P, flo
         for (int k = 0; k < 4; ++k) {
             const float ak = ac + da[k], Wk = Wc + dW[k];
             // angle difference atan2(a_k, W_k) - atan2(a_c, W_c)
-            t[k] = V.Du * atan2f(fmaf(da[k], Wc, -ac * dW[k]), fmaf(Wk, Wc, ak * ac));
-            const float rho = sqrtf(fmaf(ak, ak, Wk * Wk));
-            mn = fminf(mn, rho);
-            mx = fmaxf(mx, rho);
+            t[k] = V.Du * atan2_small(fmaf(da[k], Wc, -ac * dW[k]), fmaf(Wk, Wc, ak * ac));
+            const float rho2 = fmaf(ak, ak, Wk * Wk);   // squared distances: two roots below
+            mn = fminf(mn, rho2);
+            mx = fmaxf(mx, rho2);
         }
+        mn = sqrtf(mn);
+        mx = sqrtf(mx);
     }
     const float of = floorf(fminf(fmaxf(uc, -1.0e7f), 1.0e7f));
     const float base = uc - of;
@@ -2157,9 +2171,12 @@ __device__ __forceinline__ void dd_circ_gather(const Params &P, const float *__r
 // of sf_bwd_fast (running integral of each detector row, one load per row) with the K + 1
 // cells of the chunk carried separately, since the transaxial weights differ per voxel: voxel
 // z gathers sum_k w_k(z) (D_k(z + 1) - D_k(z)).  The corners are expanded about the chunk's
-// first slice and face as in the forward runs.  Returns false, having added nothing, when the
-// chunk's corner orders change, its faces overlap or are wider than a row, or a corner's
-// depth is not positive; the caller then takes the per-voxel path.
+// first slice and face as in the forward runs.  A face's v-interval is spanned by two corners
+// (the same at both ends of the chunk: two lines) or, in the chunk where the nearest and
+// farthest corners trade places, by the minimum and maximum of all four.  Returns false,
+// having added nothing, when the chunk's transaxial corner order changes, its faces overlap or
+// are wider than a row, or a corner's depth is not positive; the caller then takes the
+// per-voxel path.
 template <int K>
 __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
                                              const NCView &w, const float *__restrict__ yv,
@@ -2177,6 +2194,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
     // transaxial corners about slice zc0 (columns), sorted by u there, with u at the last slice
     float T0[4], ts[4], tc[4], ke[4];
     // faces: the corners with the smallest / largest v at face zc0 and at face zc0 + NQ
+    float NVk[4], DVk[4];
     float NVn = 0.0f, DVn = 1.0f, NVx = 0.0f, DVx = 1.0f;
     float vn0 = 3.0e38f, vx0 = -3.0e38f, vn1 = 3.0e38f, vx1 = -3.0e38f;
     int in0 = 0, ix0 = 0, in1 = 0, ix1 = 0;
@@ -2192,6 +2210,8 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         T0[k] += V.cu;
         ke[k] = fmaf(jl, fmaf(jl, tc[k], ts[k]), T0[k]);
         const float NV = V.Dv * fmaf(sx, V.ev[0], fmaf(sy, V.ev[1], Hf));
+        NVk[k] = NV;
+        DVk[k] = DV;
         const float a = fdiv(NV, DV), b = fdiv(fmaf(fq, w.aV, NV), fmaf(fq, w.bW, DV));
         if (a < vn0) { vn0 = a; in0 = k; NVn = NV; DVn = DV; }
         if (a > vx0) { vx0 = a; ix0 = k; NVx = NV; DVx = DV; }
@@ -2207,18 +2227,34 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
         ke[i] = sw ? ke[j] : a3; ke[j] = sw ? a3 : ke[j];
     };
     ce(0, 1); ce(2, 3); ce(0, 2); ce(1, 3); ce(1, 2);
-    float pa, ps, pc2, qa, qs, qc2;
-    nc_expand(NVn, DVn, w.aV, w.bW, pa, ps, pc2);
-    nc_expand(NVx, DVx, w.aV, w.bW, qa, qs, qc2);
-    pa += V.cv;
-    qa += V.cv;
-    auto pf = [&](int f) { return f == 0 ? pa : fmaf((float)f, fmaf((float)f, pc2, ps), pa); };
-    auto qf = [&](int f) { return f == 0 ? qa : fmaf((float)f, fmaf((float)f, qc2, qs), qa); };
+    // face lines: E[0] the lowest corner and E[1] the highest (two lines), or E[k] corner k
+    const bool two = in0 == in1 && ix0 == ix1;
+    float E0[4], Es[4], Ec[4];
+    if (two) {
+        nc_expand(NVn, DVn, w.aV, w.bW, E0[0], Es[0], Ec[0]);
+        nc_expand(NVx, DVx, w.aV, w.bW, E0[1], Es[1], Ec[1]);
+        E0[2] = E0[0], Es[2] = Es[0], Ec[2] = Ec[0];
+        E0[3] = E0[1], Es[3] = Es[1], Ec[3] = Ec[1];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            nc_expand(NVk[k], DVk[k], w.aV, w.bW, E0[k], Es[k], Ec[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        E0[k] += V.cv;
+    auto ef = [&](int k, int f) {
+        return f == 0 ? E0[k] : fmaf((float)f, fmaf((float)f, Ec[k], Es[k]), E0[k]);
+    };
+    auto pf4 = [&](int f) { return fminf(fminf(ef(0, f), ef(1, f)), fminf(ef(2, f), ef(3, f))); };
+    auto qf4 = [&](int f) { return fmaxf(fmaxf(ef(0, f), ef(1, f)), fmaxf(ef(2, f), ef(3, f))); };
+    // p(f + 1) - q(f) is a minimum and q(f) - p(f) a maximum of differences of corner lines
+    // that are affine in f up to the expansion's remainder, so their extremes over the chunk
+    // lie at its ends
     const float m = 1e-4f;
     const bool ok = dmin > 0.0f && ke[0] <= ke[1] && ke[1] <= ke[2] && ke[2] <= ke[3] &&
-                    in0 == in1 && ix0 == ix1 &&
-                    pf(1) - qa >= m && pf(NQ) - qf(NQ - 1) >= m &&      // disjoint, increasing
-                    qa - pa < 1.0f - m && qf(NQ) - pf(NQ) < 1.0f - m;   // narrower than a row
+                    pf4(1) - qf4(0) >= m && pf4(NQ) - qf4(NQ - 1) >= m &&     // disjoint
+                    qf4(0) - pf4(0) < 1.0f - m && qf4(NQ) - pf4(NQ) < 1.0f - m;  // narrow
     if (!ok)
         return false;
     // the chunk's cells c_lo .. c_lo + K (its corners drift by less than one cell)
@@ -2231,98 +2267,105 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
     for (int k = 0; k < 4; ++k)
         T0[k] -= o;
     const int rows = P.nv;
-    const float p0 = pa, qN = qf(NQ);
-    if (qN < 0.0f || p0 >= (float)rows)
-        return true;                       // the chunk's faces miss the detector rows
-    const bool inside = p0 >= 0.0f && qN < (float)(rows - 2) && c_lo >= 0 && c_lo + K < P.nu;
-    const uint32_t rs = (uint32_t)P.sino_row_stride;
-    uint32_t cidx[K + 1];
-    float cval[K + 1];                     // 1 for cells on the detector, else 0
-#pragma unroll
-    for (int k = 0; k <= K; ++k) {
-        const int cc = c_lo + k;
-        cidx[k] = (uint32_t)min(max(cc, 0), P.nu - 1);
-        cval[k] = (cc >= 0 && cc < P.nu) ? 1.0f : 0.0f;
-    }
-    int jc = inside ? (int)floorf(p0) : (int)floorf(fminf(fmaxf(p0, -1.0f), (float)rows));
-    float nraw[K + 1], rc[K + 1], rp[K + 1], RP2[K + 1], D2p[K + 1];
-    auto load_row = [&](int j, float (&dst)[K + 1]) {
-        if (inside) {
-            const float *rp_ = yv + (uint32_t)j * rs + (uint32_t)c_lo;
-#pragma unroll
-            for (int k = 0; k <= K; ++k)
-                dst[k] = rp_[k];
-        } else {
-            const bool jv = j >= 0 && j < rows;
-            const uint32_t off = (uint32_t)min(max(j, 0), rows - 1) * rs;
-#pragma unroll
-            for (int k = 0; k <= K; ++k)
-                dst[k] = jv ? yv[off + cidx[k]] * cval[k] : 0.0f;
-        }
-    };
-    load_row(jc, rc);
-    load_row(jc + 1, nraw);
-#pragma unroll
-    for (int k = 0; k <= K; ++k) {
-        rp[k] = 0.0f;
-        RP2[k] = 0.0f;
-        D2p[k] = 0.0f;
-    }
-    const float hamp = 0.5f * amp;         // D is carried doubled
-    // transaxial corners of the current voxel by second differences, with the corners' mean
-    // second-order coefficient (as in the forward runs)
-    const float tc2 = 0.5f * ((tc[0] + tc[1]) + (tc[2] + tc[3]));
-    float tx[4], td[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        tx[k] = T0[k];
-        td[k] = ts[k] + 0.5f * tc2;
-    }
-    const float fr = (float)rows;
-#pragma unroll
-    for (int f = 0; f <= NQ; ++f) {
-        const float p = pf(f), q = qf(f), wf = q - p;
-        const int jq = inside ? min((int)floorf(q), rows - 2)
-                              : (int)floorf(fminf(fmaxf(q, -1.0f), fr));
-        while (jc < jq) {
-#pragma unroll
-            for (int k = 0; k <= K; ++k) {
-                RP2[k] = fmaf(2.0f, rc[k], RP2[k]);
-                rp[k] = rc[k];
-                rc[k] = nraw[k];
-            }
-            ++jc;
-            load_row(jc + 1, nraw);
-        }
-        const float fjc = (float)jc;
-        const float a = fmaxf(fjc - p, 0.0f);
-        const float aw = (a * a) * fast_rcp(fmaxf(wf, 1e-30f));
-        // 2D = 2 (R(q) - J) = 2 (qr rc + RP) - (rp - rc) aw - rc wf: one line per cell, with
-        // the face's coefficients of rc and rp formed once (RP2 = 2 RP)
-        const float al = fmaf(2.0f, q - fjc, aw - wf), be = -aw;
-        float wv[K + 1];
-        if (f > 0) {
-            nc_slot_weights<K>(tx, hamp, P.eps, wv);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                tx[k] += td[k];
-                td[k] += tc2;
-            }
-        }
-        float s = 0.0f;
+    // the walk, once per face form (only the chosen one runs)
+    auto pf2 = [&](int f) { return ef(0, f); };
+    auto qf2 = [&](int f) { return ef(1, f); };
+    auto walk = [&](auto pf, auto qf) -> bool {
+        const float p0 = pf(0), qN = qf(NQ);
+        if (qN < 0.0f || p0 >= (float)rows)
+            return true;                       // the chunk's faces miss the detector rows
+        const bool inside = p0 >= 0.0f && qN < (float)(rows - 2) && c_lo >= 0 &&
+                            c_lo + K < P.nu;
+        const uint32_t rs = (uint32_t)P.sino_row_stride;
+        uint32_t cidx[K + 1];
+        float cval[K + 1];                     // 1 for cells on the detector, else 0
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
-            const float D2 = fmaf(al, rc[k], fmaf(be, rp[k], RP2[k]));
-            if (f > 0)
-                s = fmaf(wv[k], D2 - D2p[k], s);
-            D2p[k] = D2;
+            const int cc = c_lo + k;
+            cidx[k] = (uint32_t)min(max(cc, 0), P.nu - 1);
+            cval[k] = (cc >= 0 && cc < P.nu) ? 1.0f : 0.0f;
         }
-        if (f > 0) {
-            acc[f - 1] += s;
-            asm volatile("" : "+v"(acc[f - 1]));
+        int jc = inside ? (int)floorf(p0) : (int)floorf(fminf(fmaxf(p0, -1.0f), (float)rows));
+        float nraw[K + 1], rc[K + 1], rp[K + 1], RP2[K + 1], D2p[K + 1];
+        auto load_row = [&](int j, float (&dst)[K + 1]) {
+            if (inside) {
+                const float *rp_ = yv + (uint32_t)j * rs + (uint32_t)c_lo;
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+                    dst[k] = rp_[k];
+            } else {
+                const bool jv = j >= 0 && j < rows;
+                const uint32_t off = (uint32_t)min(max(j, 0), rows - 1) * rs;
+#pragma unroll
+                for (int k = 0; k <= K; ++k)
+                    dst[k] = jv ? yv[off + cidx[k]] * cval[k] : 0.0f;
+            }
+        };
+        load_row(jc, rc);
+        load_row(jc + 1, nraw);
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            rp[k] = 0.0f;
+            RP2[k] = 0.0f;
+            D2p[k] = 0.0f;
         }
-    }
-    return true;
+        const float hamp = 0.5f * amp;         // D is carried doubled
+        // transaxial corners of the current voxel by second differences, with the corners' mean
+        // second-order coefficient (as in the forward runs)
+        const float tc2 = 0.5f * ((tc[0] + tc[1]) + (tc[2] + tc[3]));
+        float tx[4], td[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            tx[k] = T0[k];
+            td[k] = ts[k] + 0.5f * tc2;
+        }
+        const float fr = (float)rows;
+#pragma unroll
+        for (int f = 0; f <= NQ; ++f) {
+            const float p = pf(f), q = qf(f), wf = q - p;
+            const int jq = inside ? min((int)floorf(q), rows - 2)
+                                  : (int)floorf(fminf(fmaxf(q, -1.0f), fr));
+            while (jc < jq) {
+#pragma unroll
+                for (int k = 0; k <= K; ++k) {
+                    RP2[k] = fmaf(2.0f, rc[k], RP2[k]);
+                    rp[k] = rc[k];
+                    rc[k] = nraw[k];
+                }
+                ++jc;
+                load_row(jc + 1, nraw);
+            }
+            const float fjc = (float)jc;
+            const float a = fmaxf(fjc - p, 0.0f);
+            const float aw = (a * a) * fast_rcp(fmaxf(wf, 1e-30f));
+            // 2D = 2 (R(q) - J) = 2 (qr rc + RP) - (rp - rc) aw - rc wf: one line per cell, with
+            // the face's coefficients of rc and rp formed once (RP2 = 2 RP)
+            const float al = fmaf(2.0f, q - fjc, aw - wf), be = -aw;
+            float wv[K + 1];
+            if (f > 0) {
+                nc_slot_weights<K>(tx, hamp, P.eps, wv);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    tx[k] += td[k];
+                    td[k] += tc2;
+                }
+            }
+            float s = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
+                const float D2 = fmaf(al, rc[k], fmaf(be, rp[k], RP2[k]));
+                if (f > 0)
+                    s = fmaf(wv[k], D2 - D2p[k], s);
+                D2p[k] = D2;
+            }
+            if (f > 0) {
+                acc[f - 1] += s;
+                asm volatile("" : "+v"(acc[f - 1]));
+            }
+        }
+        return true;
+    };
+    return two ? walk(pf2, qf2) : walk(pf4, qf4);
 }
 
 // ============================================================================================
@@ -2335,7 +2378,7 @@ __device__ __forceinline__ bool nc_bwd_chunk(const ViewRec &V, const Params &P,
 #define CTP_BWD_SF_BLOCKS 8
 #endif
 #ifndef CTP_BWD_NC_BLOCKS
-#define CTP_BWD_NC_BLOCKS 1
+#define CTP_BWD_NC_BLOCKS 4   // non-circular: at most 128 VGPRs (K = 4 had taken 131)
 #endif
 template <int GEOM, int METHOD>
 constexpr int bwd_min_blocks()
