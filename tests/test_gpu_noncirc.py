@@ -82,6 +82,30 @@ def run_regime(g, run=16):
     return K <= 4 and rem < 2e-5 and drift < 0.999 and (kmax + drift) * 1.001 < K
 
 
+def extreme_corner_swaps(g, chunk=16):
+    """(column, chunk, view) triples whose lowest or highest transaxial corner, by detector row,
+    differs between the chunk's bottom face and its top face: the back projection walks these
+    chunks with four-corner faces (the others with two corner lines)."""
+    hx, hy = g.dx / 2, g.dy / 2
+    xs = (np.arange(g.nx) - (g.nx - 1) / 2) * g.dx + g.x_ofst
+    ys = (np.arange(g.ny) - (g.ny - 1) / 2) * g.dy + g.y_ofst
+    zf = (np.arange(0, g.nz + 1, chunk) - g.nz / 2) * g.dz + g.z_ofst   # chunk faces
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    count = 0
+    for b in range(g.n_views):
+        prm = {n: float(np.broadcast_to(g.param(n), (g.n_views,))[b]) for n in
+               ("theta", "phi", "psi", "sad", "x_src", "z_src")}
+        R = rot(prm["theta"], prm["phi"], prm["psi"])
+        s = R @ np.array([prm["x_src"], prm["sad"], prm["z_src"]])
+        ev, n = R[:, 2], R[:, 1]
+        v = np.array([[((np.stack([X + sx, Y + sy, np.full_like(X, z)], -1) - s) @ ev) /
+                       ((s - np.stack([X + sx, Y + sy, np.full_like(X, z)], -1)) @ n)
+                       for z in zf] for sx in (-hx, hx) for sy in (-hy, hy)])
+        lo, hi = v.argmin(0), v.argmax(0)          # per face and column
+        count += int(((lo[:-1] != lo[1:]) | (hi[:-1] != hi[1:])).sum())
+    return count
+
+
 def tilted(nx, ny, nz, nu, nv, n_views, seed, tilt_deg=1.5, d=0.5, du=0.7, sad=300.0,
            sdd=500.0, extra_theta=()):
     rng = np.random.default_rng(seed)
@@ -136,6 +160,9 @@ def test_noncirc_runs_parity(torch_gpu, orc, case):
     from paper_2503_16741_amd import ctproj
     g = tilted(**CASES[case])
     assert run_regime(g), "test geometry outside the run regime"
+    if case == "inside":
+        # the back projection's four-corner chunks are exercised
+        assert extreme_corner_swaps(g) > 0
     print(f"[noncirc] {case}: {g.nx}x{g.ny}x{g.nz}, {g.n_views} views, {g.nu}x{g.nv}", flush=True)
     plan = ctproj.ctp_plan_create(g, "sf")
     x = synth.random_volume(g, seed=11)
