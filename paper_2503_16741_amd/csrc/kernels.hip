@@ -51,6 +51,9 @@
 #ifndef CTP_FWD_WAVES_NC
 #define CTP_FWD_WAVES_NC 4   // forward, non-circular: wavefronts per SIMD the registers target
 #endif
+#ifndef CTP_FWD_XCDVIEWS
+#define CTP_FWD_XCDVIEWS 1   // forward: each XCD an eighth of the views of every strip
+#endif
 #ifndef CTP_FWD_QUADS
 #define CTP_FWD_QUADS 1   // forward: before the pairs, fast columns four per wavefront (16 slices)
 #endif
@@ -1236,15 +1239,27 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
     __shared__ float s_colrec[STAGE || STAGE_DD || STAGE_NC ? kFwdThreads / 64 : 1][kRecFields][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // XCD-aware order: work-group i runs on XCD i % 8; each XCD takes the strips
-    // s = xcd, xcd + 8, ... and walks all views of a strip in order, so the work-groups that
-    // share an XCD's L2 project neighbouring views of the same strip (their voxel wedges
-    // overlap) and every XCD gets a mix of central and edge strips.
+    // XCD-aware order: work-group i runs on XCD i % 8.  XCD x takes the x-th eighth of the
+    // views of every strip, strip by strip, so that the work-groups sharing an XCD's L2
+    // project neighbouring views of the same strip (their voxel wedges overlap) and the XCDs
+    // get equal work whatever the strip count and however the strips' work differs.  (The
+    // older order, XCD x taking all views of the strips x, x + 8, ..., left the XCDs
+    // unevenly loaded: 256^3 forward 5.67 -> 5.40 ms with this one, same bits.)
     const int n_strips = (P.nu + kStripW - 1) / kStripW;
     const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
+#if CTP_FWD_XCDVIEWS
+    const int vb = (P.v_count + 7) >> 3;
+    if (kk >= n_strips * vb)
+        return;
+    const int strip = kk / vb, vl = xcd * vb + kk % vb;
+    if (vl >= P.v_count)
+        return;
+    const int view = P.v_begin + vl;
+#else
     if (kk >= ((n_strips - xcd + 7) >> 3) * P.v_count)
         return;
     const int strip = xcd + 8 * (kk / P.v_count), view = P.v_begin + kk % P.v_count;
+#endif
     const int chunk = blockIdx.y % n_row_chunks;
     const int b = blockIdx.y / n_row_chunks;            // batch item (3D); 0 in 2D
     const int i_lo = strip * kStripW;
@@ -2756,7 +2771,8 @@ hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
     const int R = min(kRowsMax, rows_total);
     size_t lds = ((size_t)(R + 1) * fwd_row_width<GEOM, METHOD, K>() + kMaxCells) * sizeof(int);
     const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
-    dim3 grid((unsigned)(8 * ((c.n_strips + 7) / 8) * p.v_count),
+    dim3 grid((unsigned)(CTP_FWD_XCDVIEWS ? 8 * c.n_strips * ((p.v_count + 7) / 8)
+                                          : 8 * ((c.n_strips + 7) / 8) * p.v_count),
               (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
     hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(kFwdThreads), lds, st, p, views,
                        volT, qscale, sino, accumulate, nchunks);
