@@ -31,6 +31,8 @@ enum Method : int { kSF = 0, kDD = 1, kSFR = 2 };
 #define CTP_STRIPW 16
 #endif
 constexpr int kStripW = CTP_STRIPW;  // detector columns owned by one forward work-group
+constexpr int kWideStripW = 2 * kStripW;   // the same on short detectors (circular 3D)
+constexpr int kWideStripRows = 128;
 constexpr int kMaxCells = 16;    // widest supported transaxial footprint (columns)
 constexpr int kRowsMax = 512;    // detector rows (or 2D batch items) held in LDS at once
 #ifndef CTP_ZCHUNK
@@ -89,6 +91,9 @@ struct Params {
     // 3D: some view projects part of the volume beyond the detector rows (the back projection
     // then tests each chunk for faces that miss them all)
     int row_clip;
+    // forward: detector columns per work-group strip (kStripW; kWideStripW for circular 3D
+    // scans on detectors of at most kWideStripRows rows, footprints of at most 4 cells)
+    int strip_w;
 };
 
 // Kernel launchers (kernels.hip).  Return hipSuccess or the launch error.

@@ -1171,8 +1171,10 @@ template <int GEOM, int METHOD, int K>
 constexpr bool nc_fwd_runs() { return GEOM == kNonCirc && METHOD == kSF && K <= 4 && CTP_FWD_FAST; }
 // Forward LDS row: the strip plus one padding column; the non-circular runs add K columns on
 // each side.
-template <int GEOM, int METHOD, int K>
-constexpr int fwd_row_width() { return kStripW + 1 + (nc_fwd_runs<GEOM, METHOD, K>() ? 2 * K : 0); }
+// LDS row width of a forward strip of STW columns: its columns, one spare, and for the
+// non-circular runs K padding columns on each side.
+template <int GEOM, int METHOD, int K, int STW>
+constexpr int fwd_row_width() { return STW + 1 + (nc_fwd_runs<GEOM, METHOD, K>() ? 2 * K : 0); }
 
 constexpr int kListCap = 1024;
 constexpr int kLaneItems = 32;   // 2D batches up to this size: each lane scatters its own pixel
@@ -1213,7 +1215,8 @@ constexpr int fwd_waves()
 }
 constexpr int kFwdWaves = kFwdThreads / 64;
 
-template <int GEOM, int DET, int METHOD, int K>
+// STW: detector columns per strip (kStripW, or kWideStripW on short detectors).
+template <int GEOM, int DET, int METHOD, int K, int STW>
 __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd_waves<GEOM, METHOD>()))) void fwd_kernel(Params P, const ViewRec *__restrict__ views,
                                                   const float *__restrict__ volT,
                                                   const float *__restrict__ qscale,
@@ -1226,7 +1229,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
     // 31 bits); contributions are converted to integers and summed, which is order
     // independent, so an item's result is bitwise repeatable and does not depend on the
     // other items of the batch.  qscale[2 b + 1] = 2^-S undoes the scale on write-out.
-    extern __shared__ int acc_mem[];         // guard row, [R][kStripW + 1], kMaxCells of padding
+    extern __shared__ int acc_mem[];         // guard row, [R][SW], kMaxCells of padding
     __shared__ int s_count, s_next;
     __shared__ unsigned short s_list[kListCap];
     // 3D runs: each wavefront stages its tile's column parameters here (record field f of
@@ -1248,7 +1251,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
     // get equal work whatever the strip count and however the strips' work differs.  (The
     // older order, XCD x taking all views of the strips x, x + 8, ..., left the XCDs
     // unevenly loaded: 256^3 forward 5.67 -> 5.40 ms with this one, same bits.)
-    const int n_strips = (P.nu + kStripW - 1) / kStripW;
+    const int n_strips = (P.nu + STW - 1) / STW;
     const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
 #if CTP_FWD_XCDVIEWS
     const int vb = (P.v_count + 7) >> 3;
@@ -1265,13 +1268,13 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
 #endif
     const int chunk = blockIdx.y % n_row_chunks;
     const int b = blockIdx.y / n_row_chunks;            // batch item (3D); 0 in 2D
-    const int i_lo = strip * kStripW;
-    const int i_hi = min(i_lo + kStripW, P.nu);
+    const int i_lo = strip * STW;
+    const int i_hi = min(i_lo + STW, P.nu);
     const int rows_total = GEOM == kFan2D ? P.nz : P.nv;
     const int r0 = chunk * kRowsMax;
     const int R = min(kRowsMax, rows_total - r0);
     const ViewRec V = views[view];
-    constexpr int SW = fwd_row_width<GEOM, METHOD, K>();
+    constexpr int SW = fwd_row_width<GEOM, METHOD, K, STW>();
     // row -1 (the guard) absorbs emits below row 0; the non-circular runs also write up to K
     // cells on either side of the strip (padding columns, never written out)
     int *acc = acc_mem + SW + (STAGE_NC ? K : 0);
@@ -1887,8 +1890,8 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(fwd
     }
 
     // write the strip, applying the per-cell amplitude
-    for (int e = threadIdx.x; e < R * kStripW; e += blockDim.x) {
-        const int row = e / kStripW, k = e - row * kStripW;
+    for (int e = threadIdx.x; e < R * STW; e += blockDim.x) {
+        const int row = e / STW, k = e - row * STW;
         const int i = i_lo + k;
         if (i >= i_hi)
             continue;
@@ -2785,21 +2788,39 @@ __global__ __launch_bounds__(256) void amp_scale_kernel(Params P, const ViewRec 
 
 // ---- dispatch --------------------------------------------------------------------------------
 
+template <int GEOM, int DET, int METHOD, int K, int STW>
+hipError_t fwd_launch_w(const Params &p, const ViewRec *views, const float *volT,
+                        const float *qscale, float *sino, int64_t batch, int accumulate,
+                        hipStream_t st)
+{
+    const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
+    const int R = min(kRowsMax, rows_total);
+    size_t lds = ((size_t)(R + 1) * fwd_row_width<GEOM, METHOD, K, STW>() + kMaxCells) * sizeof(int);
+    const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
+    const int n_strips = (p.nu + STW - 1) / STW;
+    dim3 grid((unsigned)(CTP_FWD_XCDVIEWS ? 8 * n_strips * ((p.v_count + 7) / 8)
+                                          : 8 * ((n_strips + 7) / 8) * p.v_count),
+              (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
+    hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K, STW>), grid, dim3(kFwdThreads), lds, st,
+                       p, views, volT, qscale, sino, accumulate, nchunks);
+    return hipGetLastError();
+}
+
 template <int GEOM, int DET, int METHOD, int K>
 hipError_t fwd_launch(const Params &p, const LaunchCfg &c, const ViewRec *views,
                       const float *volT, const float *qscale, float *sino, int64_t batch,
                       int accumulate, hipStream_t st)
 {
-    const int rows_total = GEOM == kFan2D ? p.nz : p.nv;
-    const int R = min(kRowsMax, rows_total);
-    size_t lds = ((size_t)(R + 1) * fwd_row_width<GEOM, METHOD, K>() + kMaxCells) * sizeof(int);
-    const int nchunks = (rows_total + kRowsMax - 1) / kRowsMax;
-    dim3 grid((unsigned)(CTP_FWD_XCDVIEWS ? 8 * c.n_strips * ((p.v_count + 7) / 8)
-                                          : 8 * ((c.n_strips + 7) / 8) * p.v_count),
-              (unsigned)((GEOM == kFan2D ? 1 : batch) * nchunks), 1);
-    hipLaunchKernelGGL((fwd_kernel<GEOM, DET, METHOD, K>), grid, dim3(kFwdThreads), lds, st, p, views,
-                       volT, qscale, sino, accumulate, nchunks);
-    return hipGetLastError();
+    (void)c;
+    // wide strips are built for the circular 3D scans with narrow footprints (the plan sets
+    // strip_w accordingly)
+    if constexpr (GEOM == kCirc && K <= 4) {
+        if (p.strip_w == kWideStripW)
+            return fwd_launch_w<GEOM, DET, METHOD, K, kWideStripW>(p, views, volT, qscale, sino,
+                                                                   batch, accumulate, st);
+    }
+    return fwd_launch_w<GEOM, DET, METHOD, K, kStripW>(p, views, volT, qscale, sino, batch,
+                                                       accumulate, st);
 }
 
 template <int GEOM, int DET, int METHOD, int K>

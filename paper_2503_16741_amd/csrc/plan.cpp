@@ -361,7 +361,14 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     c.det = g.det;
     c.method = recon ? ctp::kSFR : method;
     c.kcells = need <= 3 ? 3 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
-    c.n_strips = (g.nu + ctp::kStripW - 1) / ctp::kStripW;
+    // Forward strips: on a short detector the strip's LDS rows are few, and wider strips share
+    // each voxel column's set-up and the tile culling over more cells (512x512x256 x 720 views
+    // on 64 rows: 25.9 -> 23.2 ms); on tall detectors 16 columns keep more work-groups per CU
+    // (256^3 x 360 on 384 rows: 5.33 ms against 5.84 at 32)
+    const int strip_w = g.kind == CTP_CONE_CIRC && nv <= ctp::kWideStripRows && c.kcells <= 4
+                            ? ctp::kWideStripW
+                            : ctp::kStripW;
+    c.n_strips = (g.nu + strip_w - 1) / strip_w;
     c.n_row_chunks = (nv + ctp::kRowsMax - 1) / ctp::kRowsMax;
     // Largest possible pre-amplitude sum of one detector cell per unit |x|: SF sums
     // footprint x amplitude, at most a few times the path through the volume box; DD sums
@@ -398,6 +405,7 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     p.v_begin = 0;
     p.v_count = g.n_views;
     p.row_clip = row_clip ? 1 : 0;
+    p.strip_w = strip_w;
     p.eps = 1e-6f;
     // non-circular SF column runs: expansion accurate to 2e-5 cells / rows, a run's footprints
     // within K + 1 cells (their union is narrower than K: widths below K - 1 plus the drift)
