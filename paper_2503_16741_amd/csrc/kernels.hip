@@ -1,14 +1,13 @@
 // kernels.hip -- gfx950 kernels of the SF / DD projector pair (paper, Section 2.3).
 //
 // Forward (y = A x, Eq. 1) is output-stationary: a work-group owns one view and a strip of
-// kStripW detector columns, accumulates every row of that strip in LDS, and walks only the
-// voxel columns whose transaxial footprint meets the strip (tile culling, then per-column
-// test).  Inside a wavefront the lanes run along z of one voxel column (or, 32 or 16 lanes
-// each, of two or four), so a column's transaxial footprint is computed once and shared by its
-// lanes, the axial
-// footprints of neighbouring lanes land in different detector rows (few LDS-atomic
-// collisions), and the volume, read from a z-fastest copy, is read with unit stride.  Each
-// strip is written once: no global atomics.
+// detector columns (kStripW; kWideStripW on short detectors), accumulates every row of that
+// strip in LDS, and walks only the voxel columns whose transaxial footprint meets the strip
+// (tile culling, then per-column test).  Inside a wavefront the lanes run along z of one
+// voxel column (or, 32 or 16 lanes each, of two or four), so a column's transaxial footprint
+// is computed once and shared by its lanes, the axial footprints of neighbouring lanes land
+// in different detector rows (few LDS-atomic collisions), and the volume, read from a
+// z-fastest copy, is read with unit stride.  Each strip is written once: no global atomics.
 //
 // Back projection (x = A^T y, Eq. 2) is voxel-stationary: each lane owns one voxel column
 // and kZChunk voxels along z, loops over all views and gathers the sinogram cells its
