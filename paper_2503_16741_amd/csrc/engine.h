@@ -31,8 +31,11 @@ enum Method : int { kSF = 0, kDD = 1, kSFR = 2 };
 #define CTP_STRIPW 16
 #endif
 constexpr int kStripW = CTP_STRIPW;  // detector columns owned by one forward work-group
-constexpr int kWideStripW = 2 * kStripW;   // the same on short detectors (circular 3D)
-constexpr int kWideStripRows = 128;
+#ifndef CTP_WIDE_STRIPW
+#define CTP_WIDE_STRIPW 64
+#endif
+constexpr int kWideStripW = CTP_WIDE_STRIPW;   // the same on short detectors (circular 3D)
+constexpr int kWideStripRows = 64;
 constexpr int kMaxCells = 16;    // widest supported transaxial footprint (columns)
 constexpr int kRowsMax = 512;    // detector rows (or 2D batch items) held in LDS at once
 #ifndef CTP_ZCHUNK

@@ -363,8 +363,9 @@ ctp_status ctp_plan_create(const ctp_geometry_desc *desc, ctp_method method, ctp
     c.kcells = need <= 3 ? 3 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
     // Forward strips: on a short detector the strip's LDS rows are few, and wider strips share
     // each voxel column's set-up and the tile culling over more cells (512x512x256 x 720 views
-    // on 64 rows: 25.9 -> 23.2 ms); on tall detectors 16 columns keep more work-groups per CU
-    // (256^3 x 360 on 384 rows: 5.33 ms against 5.84 at 32)
+    // on 64 rows, SF forward: 26.1 ms with 16 columns, 23.2 with 32, 22.5 with 64); on tall
+    // detectors 16 columns keep more work-groups per CU (256^3 x 360 on 384 rows: 5.33 ms
+    // against 5.84 at 32)
     const int strip_w = g.kind == CTP_CONE_CIRC && nv <= ctp::kWideStripRows && c.kcells <= 4
                             ? ctp::kWideStripW
                             : ctp::kStripW;
